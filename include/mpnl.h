@@ -1,0 +1,214 @@
+/*
+ * mpnl.h -- C ABI of the MI355X (gfx950) library for massively parallelisable
+ * non-linear (MPNL) uplink MIMO detection, arXiv 2409.14355 Sec. II
+ * ("Background", the MPNL paragraph).
+ *
+ * The paper states the method only in prose: before transmission the channel
+ * alone fixes the relative positions of the N_p most promising solutions;
+ * during transmission those N_p candidates are formed and processed in
+ * parallel and the best one is the detection result.  This library reads
+ * that as (readings listed in the design notes):
+ *   a1  sorted QR of every subcarrier's channel, H[:, perm] = Q R
+ *       (smallest residual column first, equal norms -> lower column index,
+ *       real positive diagonal of R);
+ *   a2  the N_p position vectors with the smallest channel-only score
+ *       sum_d R_{l,l}^2 (p_d - 1), depth d detecting row l = N-1-d, equal
+ *       scores in lexicographic order of p;
+ *   a3  rotation yt = Q^H y of every received vector;
+ *   a4  one successive-interference-cancellation descent per position
+ *       vector: at depth d the p_d-th closest constellation point to
+ *       b = yt_l - sum_{j>l} R_{l,j} s_j (distance |b - R_{l,l} c|^2, equal
+ *       distances -> lower constellation index), accumulating the distances;
+ *   a5  the smallest accumulated metric wins (equal metrics -> earliest
+ *       position vector) and its symbols are written in original user order.
+ * The model is y = H s + n; no noise variance is needed by a1-a5.
+ *
+ * Data conventions (all arrays row-major, complex = interleaved float32
+ * (re, im), i.e. the memory layout of torch.complex64):
+ *   H    (S, M, N) complex   channel of each subcarrier, rx antenna major
+ *   y    (T, S, M) complex   received vector per OFDM symbol and subcarrier
+ *   out  (T, S, N) int32     detected constellation index per user
+ *   llr  (T, S, N, b) float  max-log LLR per bit (b = bits per symbol)
+ * Constellation index i (b bits): the high b/2 bits are the binary-reflected
+ * Gray label of the in-phase PAM level, the low b/2 bits that of the
+ * quadrature level; levels are (2m - L + 1) * Delta, m = 0..L-1, L = 2^(b/2),
+ * scaled to unit average energy (Delta = 1/sqrt(2), 1/sqrt(10), 1/sqrt(42)).
+ *
+ * Every pointer passed to a detection call is a DEVICE pointer on the
+ * context's device; the caller owns it and must keep it alive until the work
+ * enqueued on `stream` has completed.  Calls only enqueue work on `stream`
+ * (a hipStream_t, NULL = the legacy default stream) and return; nothing is
+ * copied back to the host.  A context is not internally locked: use one
+ * context per host thread.  No exception crosses this interface.
+ *
+ * Inputs are not scanned for NaN/Inf: such inputs give unspecified indices
+ * (always within 0..|Q|-1) and never an out-of-bounds access.
+ */
+#ifndef MPNL_H
+#define MPNL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define MPNL_OK 0
+#define MPNL_E_INVAL (-1)       /* null pointer, a size <= 0, n_paths < 1    */
+#define MPNL_E_UNSUPPORTED (-2) /* N > M, N or M above the limits, bad mod    */
+#define MPNL_E_NOMEM (-3)       /* the context's HBM budget would be exceeded */
+#define MPNL_E_HIP (-4)         /* a HIP runtime call failed, see
+                                   mpnl_last_hip_error()                     */
+
+/* ---- limits ------------------------------------------------------------ */
+#define MPNL_MAX_USERS 32       /* N (streams / single-antenna users)        */
+#define MPNL_MAX_ANTENNAS 32    /* M (receive antennas)                      */
+#define MPNL_MAX_PATHS 4096     /* N_p after clamping to |Q|^N               */
+
+/* modulation = bits per symbol */
+#define MPNL_QPSK 2
+#define MPNL_QAM16 4
+#define MPNL_QAM64 6
+
+/* arithmetic of the path search (a4/a5); a1-a3 always run in float32 with
+   the pivot norms in float64 */
+#define MPNL_PREC_FP32 0        /* float32 residuals and metric              */
+#define MPNL_PREC_FP16 1        /* float16 R / residual operands, float32
+                                   accumulation of products and the metric  */
+#define MPNL_PREC_BF16 2        /* as FP16 with bfloat16 operands            */
+
+typedef struct mpnl_ctx mpnl_ctx;
+typedef struct mpnl_slot mpnl_slot;
+
+/* ---- lifecycle ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  `hbm_budget_bytes` caps the
+   device memory the context may hold for slot state and workspace (0 = no
+   cap).  `flags` must be 0.  On success *ctx receives the context.
+   Errors: MPNL_E_INVAL (ctx NULL, flags != 0), MPNL_E_HIP (bad device). */
+int mpnl_create(mpnl_ctx **ctx, int device, size_t hbm_budget_bytes,
+                unsigned flags);
+
+/* Free a context and every slot it still owns.  Synchronises the device.
+   NULL is accepted. */
+int mpnl_destroy(mpnl_ctx *ctx);
+
+/* Static English text for a return code. */
+const char *mpnl_strerror(int code);
+
+/* hipError_t value of the last failed HIP call in this context (0 if none). */
+int mpnl_last_hip_error(const mpnl_ctx *ctx);
+
+/* Select the path-search arithmetic (MPNL_PREC_*) for later detect calls.
+   Errors: MPNL_E_INVAL (ctx NULL or unknown precision). */
+int mpnl_set_precision(mpnl_ctx *ctx, int precision);
+
+/* Bytes of device memory the context currently holds (slots, workspace and
+   cached blocks); `in_use` receives the part not free for reuse. */
+int mpnl_memory_usage(const mpnl_ctx *ctx, size_t *held, size_t *in_use);
+
+/* ---- measurement ------------------------------------------------------------ */
+
+/* Stages reported by the kernel timers. */
+#define MPNL_STAGE_SQRD 0        /* a1 sorted QR                               */
+#define MPNL_STAGE_POSVEC 1      /* a2 position-vector set                     */
+#define MPNL_STAGE_ROTATE 2      /* a3 yt = Q^H y                              */
+#define MPNL_STAGE_PATHS 3       /* a4 + a5 path search and minimum            */
+#define MPNL_NUM_STAGES 4
+
+/* Enable (1) or disable (0) kernel timers: while enabled every kernel launch
+   of the context is bracketed by two HIP events recorded on its stream.
+   Errors: MPNL_E_INVAL. */
+int mpnl_profile_enable(mpnl_ctx *ctx, int enable);
+
+/* Wait for every timed launch, then return per stage (index MPNL_STAGE_*)
+   the summed kernel time in milliseconds and the number of launches, and
+   forget them.  Either array may be NULL.
+   Errors: MPNL_E_INVAL, MPNL_E_HIP. */
+int mpnl_profile_collect(mpnl_ctx *ctx, double *total_ms, int *launches);
+
+/* ---- one-shot detection (a1 .. a5) --------------------------------------- */
+
+/* Detect T*S received vectors that share one channel per subcarrier
+   (a slot).  n_paths (N_p) is clamped to min(n_paths, |Q|^N); with the
+   clamp reached the result is exact maximum-likelihood detection.
+   Errors: MPNL_E_INVAL, MPNL_E_UNSUPPORTED (N > M, N > 32, M > 32,
+   unknown mod, clamped N_p > MPNL_MAX_PATHS), MPNL_E_NOMEM, MPNL_E_HIP. */
+int mpnl_detect(mpnl_ctx *ctx, const void *H, const void *y, int S, int T,
+                int M, int N, int mod, int n_paths, int32_t *out,
+                void *stream);
+
+/* ---- slot-resident state (serving) ---------------------------------------- */
+
+/* Run a1 (sorted QR) and a2 (position-vector set) for one slot's channel and
+   keep Q, R, perm and the position vectors on the device until
+   mpnl_slot_release().  The channel is only read by the enqueued work.
+   On success *slot receives a handle owned by the context.
+   Errors as mpnl_detect(). */
+int mpnl_slot_prepare(mpnl_ctx *ctx, const void *H, int S, int M, int N,
+                      int mod, int n_paths, void *stream, mpnl_slot **slot);
+
+/* Run a3 .. a5 for T symbols of a prepared slot: y (T, S, M) -> out (T, S, N).
+   May be called any number of times on any stream; work on a stream other
+   than the prepare stream must be ordered after it by the caller.
+   Errors: MPNL_E_INVAL (null, T <= 0), MPNL_E_NOMEM, MPNL_E_HIP. */
+int mpnl_slot_detect(mpnl_ctx *ctx, mpnl_slot *slot, const void *y, int T,
+                     int32_t *out, void *stream);
+
+/* As mpnl_slot_detect(), plus max-log soft output from the path list: for
+   bit k of user u, llr = (min metric over paths whose symbol has bit k = 1
+   minus min metric over paths with bit k = 0) / sigma2, positive favouring
+   0, clipped to [-clip, clip] and set to +-clip when one hypothesis has no
+   path.  Bits count from the most significant bit of the index.
+   llr is (T, S, N, bits) float32.  `out` may be NULL.
+   Errors: as mpnl_slot_detect(), MPNL_E_INVAL for sigma2 <= 0 or clip <= 0. */
+int mpnl_slot_detect_soft(mpnl_ctx *ctx, mpnl_slot *slot, const void *y,
+                          int T, float sigma2, float clip, float *llr,
+                          int32_t *out, void *stream);
+
+/* Release a slot; its memory returns to the context once the work already
+   enqueued on the slot's streams has finished.  NULL is accepted. */
+int mpnl_slot_release(mpnl_ctx *ctx, mpnl_slot *slot);
+
+/* Copy a prepared slot's a1/a2 results into caller device buffers, in the
+   depth order the path search uses (depth d detects row l = N-1-d):
+     perm (S, N) int32      original user index detected at depth d
+     w (S, N) double        R_{l,l}^2, the float64 pivot norm the position
+                            set is built from (R_{l,l} = sqrt(w))
+     roff (S, N, N) complex R_{l',l} at [d][d'] for d' > d (l' = N-1-d'),
+                            other entries unspecified
+     P (S, K, N) uint8      position vectors, K = clamped N_p
+   Any pointer may be NULL to skip it.  Errors: MPNL_E_INVAL, MPNL_E_HIP. */
+int mpnl_slot_export(mpnl_ctx *ctx, const mpnl_slot *slot, int32_t *perm,
+                     double *w, void *roff, uint8_t *P, void *stream);
+
+/* Shape of a prepared slot: S, M, N, mod and the clamped path count K. */
+int mpnl_slot_info(const mpnl_slot *slot, int *S, int *M, int *N, int *mod,
+                   int *K);
+
+/* ---- uneven multi-cell batch ---------------------------------------------- */
+
+typedef struct mpnl_job {
+    const void *H;   /* (S, M, N) complex, device                          */
+    const void *y;   /* (T, S, M) complex, device                          */
+    int32_t *out;    /* (T, S, N) int32, device                             */
+    int S, T, M, N;
+    int mod;         /* MPNL_QPSK / MPNL_QAM16 / MPNL_QAM64                 */
+    int n_paths;
+} mpnl_job;
+
+/* Detect several independent jobs (cells) of different shapes with one
+   batched launch per stage: the path searches of every job run in a single
+   persistent kernel that pulls (job, subcarrier, symbol) work items from a
+   device queue.  Each job's result is identical to mpnl_detect() on it alone.
+   Errors: as mpnl_detect() for any job; nothing is enqueued on error. */
+int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs,
+                      void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPNL_H */

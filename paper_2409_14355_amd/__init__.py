@@ -1,0 +1,332 @@
+"""MI355X (gfx950) MPNL uplink MIMO detection, arXiv 2409.14355 Sec. II.
+
+Thin ctypes binding of the C ABI in ``include/mpnl.h``: the functions named
+``mpnl_*`` take the same arguments as their C counterparts (torch tensors
+stand in for device pointers, a torch stream or None for ``hipStream_t``) and
+only marshal them.  Every step of detection runs in the HIP kernels of
+``libmpnl.so``; there is no CPU fallback: if the library is missing or no GPU
+is present the calls raise.
+
+Convenience layer: :class:`Context`, :class:`Slot` and :func:`detect`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpnl.so")
+
+MPNL_OK = 0
+MPNL_E_INVAL = -1
+MPNL_E_UNSUPPORTED = -2
+MPNL_E_NOMEM = -3
+MPNL_E_HIP = -4
+MPNL_MAX_USERS = 32
+MPNL_MAX_ANTENNAS = 32
+MPNL_MAX_PATHS = 4096
+MPNL_QPSK, MPNL_QAM16, MPNL_QAM64 = 2, 4, 6
+MPNL_PREC_FP32, MPNL_PREC_FP16, MPNL_PREC_BF16 = 0, 1, 2
+
+EXPORTED = (
+    "mpnl_create", "mpnl_destroy", "mpnl_strerror", "mpnl_last_hip_error",
+    "mpnl_set_precision", "mpnl_memory_usage", "mpnl_detect", "mpnl_slot_prepare",
+    "mpnl_slot_detect", "mpnl_slot_detect_soft", "mpnl_slot_release", "mpnl_slot_export",
+    "mpnl_slot_info", "mpnl_detect_batch", "mpnl_profile_enable", "mpnl_profile_collect",
+)
+MPNL_STAGE_SQRD, MPNL_STAGE_POSVEC, MPNL_STAGE_ROTATE, MPNL_STAGE_PATHS = 0, 1, 2, 3
+STAGE_NAMES = ("sqrd", "posvec", "rotate", "paths")
+
+
+class MpnlError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {code} ({strerror(code)})")
+
+
+class mpnl_job(ctypes.Structure):
+    _fields_ = [
+        ("H", ctypes.c_void_p), ("y", ctypes.c_void_p), ("out", ctypes.c_void_p),
+        ("S", ctypes.c_int), ("T", ctypes.c_int), ("M", ctypes.c_int), ("N", ctypes.c_int),
+        ("mod", ctypes.c_int), ("n_paths", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmpnl.so (built by ``paper_2409_14355_amd/build.py``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, ip, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    L.mpnl_create.argtypes = [ctypes.POINTER(vp), ip, sz, ctypes.c_uint]
+    L.mpnl_destroy.argtypes = [vp]
+    L.mpnl_strerror.argtypes = [ip]
+    L.mpnl_strerror.restype = ctypes.c_char_p
+    L.mpnl_last_hip_error.argtypes = [vp]
+    L.mpnl_set_precision.argtypes = [vp, ip]
+    L.mpnl_memory_usage.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    L.mpnl_detect.argtypes = [vp, vp, vp, ip, ip, ip, ip, ip, ip, vp, vp]
+    L.mpnl_slot_prepare.argtypes = [vp, vp, ip, ip, ip, ip, ip, vp, ctypes.POINTER(vp)]
+    L.mpnl_slot_detect.argtypes = [vp, vp, vp, ip, vp, vp]
+    L.mpnl_slot_detect_soft.argtypes = [vp, vp, vp, ip, ctypes.c_float, ctypes.c_float, vp, vp, vp]
+    L.mpnl_slot_release.argtypes = [vp, vp]
+    L.mpnl_slot_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.mpnl_slot_info.argtypes = [vp] + [ctypes.POINTER(ip)] * 5
+    L.mpnl_detect_batch.argtypes = [vp, ctypes.POINTER(mpnl_job), ip, vp]
+    L.mpnl_profile_enable.argtypes = [vp, ip]
+    L.mpnl_profile_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ip)]
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().mpnl_strerror(code).decode()
+    except RuntimeError:
+        return "library not loaded"
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != MPNL_OK:
+        raise MpnlError(rc, what)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("device buffers are passed as torch tensors")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---- same-named wrappers of the C ABI -------------------------------------------
+
+def mpnl_create(device: int = 0, hbm_budget_bytes: int = 0, flags: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().mpnl_create(ctypes.byref(h), device, hbm_budget_bytes, flags), "mpnl_create")
+    return h.value
+
+
+def mpnl_destroy(ctx: int) -> None:
+    _check(lib().mpnl_destroy(ctx), "mpnl_destroy")
+
+
+def mpnl_strerror(code: int) -> str:
+    return strerror(code)
+
+
+def mpnl_last_hip_error(ctx: int) -> int:
+    return lib().mpnl_last_hip_error(ctx)
+
+
+def mpnl_set_precision(ctx: int, precision: int) -> None:
+    _check(lib().mpnl_set_precision(ctx, precision), "mpnl_set_precision")
+
+
+def mpnl_memory_usage(ctx: int) -> tuple[int, int]:
+    held, used = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().mpnl_memory_usage(ctx, ctypes.byref(held), ctypes.byref(used)), "mpnl_memory_usage")
+    return held.value, used.value
+
+
+def mpnl_detect(ctx: int, H, y, S: int, T: int, M: int, N: int, mod: int, n_paths: int, out,
+                stream=None) -> None:
+    _check(lib().mpnl_detect(ctx, _ptr(H), _ptr(y), S, T, M, N, mod, n_paths, _ptr(out),
+                             _stream(stream)), "mpnl_detect")
+
+
+def mpnl_slot_prepare(ctx: int, H, S: int, M: int, N: int, mod: int, n_paths: int,
+                      stream=None) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().mpnl_slot_prepare(ctx, _ptr(H), S, M, N, mod, n_paths, _stream(stream),
+                                   ctypes.byref(h)), "mpnl_slot_prepare")
+    return h.value
+
+
+def mpnl_slot_detect(ctx: int, slot: int, y, T: int, out, stream=None) -> None:
+    _check(lib().mpnl_slot_detect(ctx, slot, _ptr(y), T, _ptr(out), _stream(stream)),
+           "mpnl_slot_detect")
+
+
+def mpnl_slot_detect_soft(ctx: int, slot: int, y, T: int, sigma2: float, clip: float, llr,
+                          out=None, stream=None) -> None:
+    _check(lib().mpnl_slot_detect_soft(ctx, slot, _ptr(y), T, sigma2, clip, _ptr(llr), _ptr(out),
+                                       _stream(stream)), "mpnl_slot_detect_soft")
+
+
+def mpnl_slot_release(ctx: int, slot: int) -> None:
+    _check(lib().mpnl_slot_release(ctx, slot), "mpnl_slot_release")
+
+
+def mpnl_slot_export(ctx: int, slot: int, perm=None, w=None, roff=None, P=None,
+                     stream=None) -> None:
+    _check(lib().mpnl_slot_export(ctx, slot, _ptr(perm), _ptr(w), _ptr(roff), _ptr(P),
+                                  _stream(stream)), "mpnl_slot_export")
+
+
+def mpnl_slot_info(slot: int) -> dict:
+    v = [ctypes.c_int() for _ in range(5)]
+    _check(lib().mpnl_slot_info(slot, *[ctypes.byref(x) for x in v]), "mpnl_slot_info")
+    return dict(zip(("S", "M", "N", "mod", "K"), (x.value for x in v)))
+
+
+def mpnl_detect_batch(ctx: int, jobs: Sequence[dict], stream=None) -> None:
+    arr = (mpnl_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        S, M, N = j["H"].shape
+        T = j["y"].shape[0]
+        arr[i] = mpnl_job(_ptr(j["H"]), _ptr(j["y"]), _ptr(j["out"]), S, T, M, N, j["mod"],
+                          j["n_paths"])
+    _check(lib().mpnl_detect_batch(ctx, arr, len(jobs), _stream(stream)), "mpnl_detect_batch")
+
+
+def mpnl_profile_enable(ctx: int, enable: bool) -> None:
+    _check(lib().mpnl_profile_enable(ctx, 1 if enable else 0), "mpnl_profile_enable")
+
+
+def mpnl_profile_collect(ctx: int) -> dict:
+    """-> {stage name: (total milliseconds, launches)} since the last collect."""
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_int * 4)()
+    _check(lib().mpnl_profile_collect(ctx, ms, n), "mpnl_profile_collect")
+    return {STAGE_NAMES[i]: (ms[i], n[i]) for i in range(4)}
+
+
+# ---- convenience layer ------------------------------------------------------------
+
+def _shapes(H, y):
+    if H.dim() != 3 or y.dim() != 3:
+        raise ValueError("H must be (S, M, N) and y (T, S, M)")
+    S, M, N = H.shape
+    T = y.shape[0]
+    if y.shape[1] != S or y.shape[2] != M:
+        raise ValueError(f"y shape {tuple(y.shape)} does not match H {tuple(H.shape)}")
+    return S, T, M, N
+
+
+class Slot:
+    """Channel state of one slot kept on the device (a1 + a2 done)."""
+
+    def __init__(self, ctx: "Context", handle: int, S: int, M: int, N: int, mod: int):
+        self.ctx, self.handle, self.S, self.M, self.N, self.mod = ctx, handle, S, M, N, mod
+
+    def detect(self, y, out=None, stream=None):
+        import torch
+        T = y.shape[0]
+        if out is None:
+            out = torch.empty((T, self.S, self.N), dtype=torch.int32, device=y.device)
+        mpnl_slot_detect(self.ctx.handle, self.handle, y, T, out, stream)
+        return out
+
+    def detect_soft(self, y, sigma2: float, clip: float = 1e4, out=None, stream=None):
+        import torch
+        T = y.shape[0]
+        llr = torch.empty((T, self.S, self.N, self.mod), dtype=torch.float32, device=y.device)
+        mpnl_slot_detect_soft(self.ctx.handle, self.handle, y, T, sigma2, clip, llr, out, stream)
+        return llr
+
+    def export(self, stream=None) -> dict:
+        import torch
+        info = mpnl_slot_info(self.handle)
+        S, N, K = info["S"], info["N"], info["K"]
+        dev = f"cuda:{self.ctx.device}"
+        perm = torch.empty((S, N), dtype=torch.int32, device=dev)
+        w = torch.empty((S, N), dtype=torch.float64, device=dev)
+        roff = torch.empty((S, N, N), dtype=torch.complex64, device=dev)
+        P = torch.empty((S, K, N), dtype=torch.uint8, device=dev)
+        mpnl_slot_export(self.ctx.handle, self.handle, perm, w, roff, P, stream)
+        return dict(perm=perm, w=w, roff=roff, P=P, K=K)
+
+    def release(self):
+        if self.handle:
+            mpnl_slot_release(self.ctx.handle, self.handle)
+            self.handle = 0
+
+
+class Context:
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.device = device
+        self.handle = mpnl_create(device, hbm_budget_bytes, 0)
+
+    def close(self):
+        if self.handle:
+            mpnl_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_precision(self, precision: int):
+        mpnl_set_precision(self.handle, precision)
+
+    def memory_usage(self):
+        return mpnl_memory_usage(self.handle)
+
+    def profile(self, enable: bool = True):
+        mpnl_profile_enable(self.handle, enable)
+
+    def profile_collect(self) -> dict:
+        return mpnl_profile_collect(self.handle)
+
+    def detect(self, H, y, mod: int, n_paths: int, out=None, stream=None):
+        import torch
+        S, T, M, N = _shapes(H, y)
+        if out is None:
+            out = torch.empty((T, S, N), dtype=torch.int32, device=H.device)
+        mpnl_detect(self.handle, H, y, S, T, M, N, mod, n_paths, out, stream)
+        return out
+
+    def slot_prepare(self, H, mod: int, n_paths: int, stream=None) -> Slot:
+        S, M, N = H.shape
+        h = mpnl_slot_prepare(self.handle, H, S, M, N, mod, n_paths, stream)
+        return Slot(self, h, S, M, N, mod)
+
+    def detect_batch(self, jobs: Sequence[dict], stream=None):
+        import torch
+        for j in jobs:
+            if j.get("out") is None:
+                S, T, M, N = _shapes(j["H"], j["y"])
+                j["out"] = torch.empty((T, S, N), dtype=torch.int32, device=j["H"].device)
+        mpnl_detect_batch(self.handle, jobs, stream)
+        return [j["out"] for j in jobs]
+
+
+_default_ctx: Optional[Context] = None
+
+
+def detect(H, y, mod: int, n_paths: int, out=None, stream=None):
+    """detect(H (S,M,N) c64, y (T,S,M) c64, mod, n_paths) -> (T,S,N) int32 indices."""
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context(H.device.index or 0)
+    return _default_ctx.detect(H, y, mod, n_paths, out, stream)

@@ -1,0 +1,56 @@
+// Internal interface between the host runtime and the gfx950 kernels of the
+// MPNL detection library.  Not part of the public ABI (see include/mpnl.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpnl {
+
+// Per-slot device state written by the sorted-QR and position-set kernels.
+// Everything is stored in *depth order*: depth d detects row l = N-1-d of R.
+struct SlotDev {
+    int S, M, N, bits, K;  // K = clamped number of paths
+    int NP;                // position-vector row stride in bytes (N rounded up to 4)
+    float2 *Qd;            // (S, M, N)  column d = Q[:, N-1-d]
+    float2 *roff;          // (S, N, N)  [d][d'] = R[N-1-d'][N-1-d] for d' > d
+    float4 *diag;          // (S, N)     (R_ll, R_ll*Delta, 1/(2 R_ll Delta) or 0, 0)
+    double *wd;            // (S, N)     R_ll^2 from the float64 pivot norm
+    int32_t *permd;        // (S, N)     original user detected at depth d
+    uint8_t *P;            // (S, K, NP) ranks 1..|Q| per depth, padded with 1
+    uint32_t *rec;         // (S, N, K)  position-set back pointers when they do not fit in LDS
+};
+
+// Work item of the batched path search: one job (cell) of an uneven batch.
+struct JobDev {
+    const float2 *yt;      // (T, S, N) rotated received vectors, depth order
+    const float2 *roff;
+    const float4 *diag;
+    const int32_t *permd;
+    const uint8_t *P;
+    int32_t *out;          // (T, S, N)
+    int S, T, N, K, NP;
+    int item_begin;        // first global work item of this job
+};
+
+// Kernel launchers (enqueue only; return hipError_t of the launch).
+// a1; also writes R * Delta as half2 / bf16x2 for the reduced-precision path search.
+hipError_t launch_sqrd_q(const float2 *H, const SlotDev &sd, uint32_t *roff_h, uint32_t *roff_b,
+                         hipStream_t st);
+hipError_t launch_posvec(const SlotDev &sd, hipStream_t st);
+hipError_t launch_rotate(const SlotDev &sd, const float2 *y, int T, float2 *yt, hipStream_t st);
+// roffq: the half2 / bf16x2 copy of R matching `precision` (null for float32).
+hipError_t launch_path_search_q(const SlotDev &sd, const float2 *yt, int T, int32_t *out,
+                                int precision, const uint32_t *roffq, hipStream_t st);
+hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, float sigma2,
+                                   float clip, float *llr, int32_t *out, hipStream_t st);
+// Batched path search over many jobs sharing (NMAX bucket, bits); one persistent launch.
+hipError_t launch_path_search_batch(const JobDev *jobs_dev, int n_jobs, int total_items,
+                                    int nmax_bucket, int bits, int max_threads,
+                                    unsigned *queue_counter, int grid, hipStream_t st);
+
+size_t posvec_lds_bytes(int N, int K, bool rec_in_lds);
+bool posvec_rec_fits_lds(int N, int K);
+int nmax_bucket(int N);
+
+}  // namespace mpnl

@@ -1,0 +1,559 @@
+// a1 (sorted QR), a2 (position-vector set) and a3 (rotation on MFMA) kernels
+// of the MPNL uplink detector (arXiv 2409.14355, Sec. II), gfx950.
+#include "device_common.h"
+
+namespace mpnl {
+namespace dev {
+
+// ============================================================================
+// a1: sorted QR.
+// Lane c of a half-wave holds column c of H (rows padded with zeros to MMAX).
+// Step i: every column not yet placed computes its residual norm^2 over rows
+// >= i in float64; the smallest (equal: lower column index) is placed at
+// position i.  Its Householder reflector H_i = I - tau v v^H maps the
+// residual onto e_i; it is broadcast through LDS and applied to every column
+// not yet placed.  Row i of R is then rotated by conj(phi_i) so that R_ii is
+// real and positive, and Q's column i by phi_i (Q R is unchanged).
+// Q = H_0 H_1 ... H_{N-1} [I; 0] is accumulated per column at the end.
+// ============================================================================
+struct SqrdArgs {
+    const float2 *H;
+    int S, M, N;
+    float delta;
+    SlotDev sd;
+    uint32_t *roff_h;  // (S, N, N) half2 of R * Delta  (MPNL_PREC_FP16)
+    uint32_t *roff_b;  // (S, N, N) bf16x2 of R * Delta (MPNL_PREC_BF16)
+};
+
+__device__ __forceinline__ uint32_t pack_half2(float x, float y)
+{
+    half2_t h;
+    h.x = (_Float16)x;
+    h.y = (_Float16)y;
+    return __builtin_bit_cast(uint32_t, h);
+}
+
+__device__ __forceinline__ uint32_t bf16_bits(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u)  // NaN: keep it a NaN
+        return (u >> 16) | 0x40u;
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;  // round to nearest even
+}
+
+template <int MMAX>
+__global__ __launch_bounds__(64) void sqrd_kernel(SqrdArgs a)
+{
+    __shared__ float2 V[2][kMaxN][MMAX];
+    __shared__ float TAU[2][kMaxN];
+    __shared__ float2 PHI[2][kMaxN];
+
+    const int half = threadIdx.x >> 5;
+    const int c = threadIdx.x & 31;
+    const int s = blockIdx.x * 2 + half;
+    const int M = a.M, N = a.N;
+    const bool active = (s < a.S) && (c < N);
+
+    float2 col[MMAX];
+#pragma unroll
+    for (int m = 0; m < MMAX; ++m) {
+        col[m] = make_float2(0.f, 0.f);
+        if (active && m < M)
+            col[m] = a.H[((size_t)s * M + m) * N + c];
+    }
+
+    bool placed = false;
+    int pos = 0;
+    double wnorm = 0.0;
+
+#pragma unroll
+    for (int i = 0; i < MMAX; ++i) {
+        if (i < N) {
+        double nu = 0.0;
+#pragma unroll
+        for (int m = i; m < MMAX; ++m)
+            nu += (double)col[m].x * (double)col[m].x + (double)col[m].y * (double)col[m].y;
+
+        const bool cand = active && !placed;
+        double key = cand ? nu : (double)INFINITY;
+        int id = cand ? c : (1 << 20);
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) {
+            const double ok = __shfl_xor(key, off, 32);
+            const int oid = __shfl_xor(id, off, 32);
+            if (ok < key || (ok == key && oid < id)) {
+                key = ok;
+                id = oid;
+            }
+        }
+        const bool me = cand && (c == id);
+        if (me) {
+            const float alpha = (float)sqrt(nu);
+            const float2 x0 = col[i];
+            const float ax0 = sqrtf(x0.x * x0.x + x0.y * x0.y);
+            float2 e = make_float2(1.f, 0.f);
+            if (ax0 > 0.f)
+                e = make_float2(x0.x / ax0, x0.y / ax0);
+#pragma unroll
+            for (int m = 0; m < MMAX; ++m) {
+                float2 v = (m < i) ? make_float2(0.f, 0.f) : col[m];
+                if (m == i) {
+                    v.x += e.x * alpha;
+                    v.y += e.y * alpha;
+                }
+                V[half][i][m] = v;
+            }
+            TAU[half][i] = (alpha > 0.f) ? 1.f / (alpha * (alpha + ax0)) : 0.f;
+            PHI[half][i] = make_float2(-e.x, -e.y);
+            placed = true;
+            pos = i;
+            wnorm = nu;
+        }
+        __syncthreads();
+        if (active && (!placed || me)) {
+            const float tau = TAU[half][i];
+            float gr = 0.f, gi = 0.f;  // v^H col
+#pragma unroll
+            for (int m = i; m < MMAX; ++m) {
+                const float2 v = V[half][i][m];
+                gr = fmaf(v.x, col[m].x, gr);
+                gr = fmaf(v.y, col[m].y, gr);
+                gi = fmaf(v.x, col[m].y, gi);
+                gi = fmaf(-v.y, col[m].x, gi);
+            }
+            gr *= tau;
+            gi *= tau;
+#pragma unroll
+            for (int m = i; m < MMAX; ++m) {
+                const float2 v = V[half][i][m];
+                col[m].x -= gr * v.x - gi * v.y;
+                col[m].y -= gr * v.y + gi * v.x;
+            }
+            const float2 ph = PHI[half][i];  // row i *= conj(phi_i)
+            const float xr = col[i].x * ph.x + col[i].y * ph.y;
+            const float xi = col[i].y * ph.x - col[i].x * ph.y;
+            col[i] = make_float2(xr, xi);
+            if (me) {
+                col[i] = make_float2((float)sqrt(nu), 0.f);
+#pragma unroll
+                for (int m = i + 1; m < MMAX; ++m)
+                    col[m] = make_float2(0.f, 0.f);
+            }
+        }
+        }
+    }
+
+    // ---- outputs of R, in depth order ----
+    const int d = N - 1 - pos;
+    if (active) {
+        const size_t sN = (size_t)s * N;
+        const float rll = (float)sqrt(wnorm);
+        const float aa = rll * a.delta;
+        a.sd.diag[sN + d] = make_float4(rll, aa, aa > 0.f ? 1.f / (2.f * aa) : 0.f, 0.f);
+        a.sd.wd[sN + d] = wnorm;
+        a.sd.permd[sN + d] = c;
+#pragma unroll
+        for (int m = 0; m < MMAX; ++m) {
+            if (m < pos) {
+                const int d2 = N - 1 - m;
+                const size_t o = (sN + d) * N + d2;
+                a.sd.roff[o] = col[m];
+                a.roff_h[o] = pack_half2(col[m].x * a.delta, col[m].y * a.delta);
+                a.roff_b[o] = bf16_bits(col[m].x * a.delta) | (bf16_bits(col[m].y * a.delta) << 16);
+            }
+        }
+    }
+
+    // ---- Q column = phi_pos * H_0 ... H_pos e_pos ----
+    float2 q[MMAX];
+#pragma unroll
+    for (int m = 0; m < MMAX; ++m)
+        q[m] = make_float2(m == pos ? 1.f : 0.f, 0.f);
+#pragma unroll
+    for (int j = MMAX - 1; j >= 0; --j) {
+        if (j < N && active && j <= pos) {
+            const float tau = TAU[half][j];
+            float gr = 0.f, gi = 0.f;
+#pragma unroll
+            for (int m = j; m < MMAX; ++m) {
+                const float2 v = V[half][j][m];
+                gr = fmaf(v.x, q[m].x, gr);
+                gr = fmaf(v.y, q[m].y, gr);
+                gi = fmaf(v.x, q[m].y, gi);
+                gi = fmaf(-v.y, q[m].x, gi);
+            }
+            gr *= tau;
+            gi *= tau;
+#pragma unroll
+            for (int m = j; m < MMAX; ++m) {
+                const float2 v = V[half][j][m];
+                q[m].x -= gr * v.x - gi * v.y;
+                q[m].y -= gr * v.y + gi * v.x;
+            }
+        }
+    }
+    if (active) {
+        const float2 ph = PHI[half][pos];
+#pragma unroll
+        for (int m = 0; m < MMAX; ++m) {
+            if (m < M) {
+                const float2 z = q[m];
+                a.sd.Qd[((size_t)s * M + m) * N + d] =
+                    make_float2(z.x * ph.x - z.y * ph.y, z.x * ph.y + z.y * ph.x);
+            }
+        }
+    }
+}
+
+// ============================================================================
+// a2: position-vector set.
+// The score of a position vector is sum_d w_d (p_d - 1), accumulated in depth
+// order in float64 exactly as written (product, then sum; no contraction).
+// Depth by depth, the list of the K cheapest prefixes (in (score, lexical)
+// order) is extended: candidates are (prefix i, k) with score
+// sc_i + w_d * k, k = 0..|Q|-1.  Because every copy "list + k w_d" is a
+// shifted copy of the sorted list, the top-K of their union is built as
+//     Z_0 = list,  Z_m = topK(list  U  shift(Z_{m-1})),
+// stopping when the cheapest entry with p_d = m+1 can no longer enter.
+// Each merge is a merge-path over two sorted lists in LDS.  Ties in score are
+// ordered by the lexical rank of the parent prefix, then k, which is the
+// lexicographic order of the extended prefixes.  Back pointers
+// (parent, k) per depth rebuild the vectors at the end.
+// ============================================================================
+struct PosArgs {
+    const double *w;  // (S, N)
+    int S, N, nq, K, NP;
+    uint8_t *P;       // (S, K, NP)
+    uint32_t *rec_g;  // (S, N, K) when the back pointers do not fit in LDS
+};
+
+__device__ __forceinline__ bool key_less(double sa, int la, int ka, double sb, int lb, int kb)
+{
+    return sa < sb || (sa == sb && (la < lb || (la == lb && ka < kb)));
+}
+
+__device__ __forceinline__ double cand_score(double parent, double w, int k)
+{
+    return __dadd_rn(parent, __dmul_rn(w, (double)k));
+}
+
+template <bool REC_LDS>
+__global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int K = a.K, N = a.N, nq = a.nq;
+    const int lane = threadIdx.x;
+    const int s = blockIdx.x;
+
+    double *A_sc = (double *)smem;
+    double *Zs[2] = {A_sc + K, A_sc + 2 * K};
+    uint16_t *A_lx = (uint16_t *)(A_sc + 3 * K);
+    uint16_t *Zp[2] = {A_lx + K, A_lx + 2 * K};
+    uint16_t *Zk[2] = {A_lx + 3 * K, A_lx + 4 * K};
+    uint32_t *cnt = (uint32_t *)(A_lx + ((5 * K + 1) & ~1));
+    uint32_t *rec = REC_LDS ? (cnt + K) : (a.rec_g + (size_t)s * N * K);
+
+    if (lane == 0) {
+        A_sc[0] = 0.0;
+        A_lx[0] = 0;
+    }
+    int n = 1;
+    __syncthreads();
+
+    for (int d = 0; d < N; ++d) {
+        const double wd = a.w[(size_t)s * N + d];
+        int cur = 0;
+        for (int i = lane; i < n; i += 64) {
+            Zs[0][i] = A_sc[i];
+            Zp[0][i] = (uint16_t)i;
+            Zk[0][i] = 0;
+        }
+        int zn = n;
+        __syncthreads();
+        for (int m = 1; m < nq; ++m) {
+            if (zn == K) {
+                const double nm = cand_score(A_sc[0], wd, m);
+                const int zp = Zp[cur][K - 1];
+                if (!key_less(nm, A_lx[0], m, Zs[cur][K - 1], A_lx[zp], Zk[cur][K - 1]))
+                    break;
+            }
+            // merge list A (k = 0) with B = shift(Z_cur) into Z_nxt
+            const int nxt = cur ^ 1;
+            const int total = min(K, n + zn);
+            const int chunk = (total + 63) / 64;
+            const int p0 = min(total, lane * chunk);
+            const int p1 = min(total, p0 + chunk);
+            const double *zs = Zs[cur];
+            const uint16_t *zp = Zp[cur];
+            const uint16_t *zk = Zk[cur];
+            if (p0 < p1) {
+                int lo = max(0, p0 - zn), hi = min(p0, n);
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int j = p0 - mid - 1;
+                    const int par = zp[j];
+                    const int kb = zk[j] + 1;
+                    const double sb = cand_score(A_sc[par], wd, kb);
+                    if (key_less(A_sc[mid], A_lx[mid], 0, sb, A_lx[par], kb))
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                int i = lo, j = p0 - lo;
+                for (int p = p0; p < p1; ++p) {
+                    bool takeA;
+                    double sb = 0.0;
+                    int par = 0, kb = 0;
+                    if (j < zn) {
+                        par = zp[j];
+                        kb = zk[j] + 1;
+                        sb = cand_score(A_sc[par], wd, kb);
+                    }
+                    if (i >= n)
+                        takeA = false;
+                    else if (j >= zn)
+                        takeA = true;
+                    else
+                        takeA = key_less(A_sc[i], A_lx[i], 0, sb, A_lx[par], kb);
+                    if (takeA) {
+                        Zs[nxt][p] = A_sc[i];
+                        Zp[nxt][p] = (uint16_t)i;
+                        Zk[nxt][p] = 0;
+                        ++i;
+                    } else {
+                        Zs[nxt][p] = sb;
+                        Zp[nxt][p] = (uint16_t)par;
+                        Zk[nxt][p] = (uint16_t)kb;
+                        ++j;
+                    }
+                }
+            }
+            __syncthreads();
+            cur = nxt;
+            zn = total;
+        }
+        // lexical ranks of the new prefixes: children of a parent are k = 0..c-1
+        for (int i = lane; i < n; i += 64)
+            cnt[i] = 0;
+        __syncthreads();
+        for (int j = lane; j < zn; j += 64)
+            atomicMax(&cnt[A_lx[Zp[cur][j]]], (uint32_t)Zk[cur][j] + 1u);
+        __syncthreads();
+        {  // exclusive scan of cnt[0..n)
+            const int ch = (n + 63) / 64;
+            const int q0 = min(n, lane * ch), q1 = min(n, q0 + ch);
+            uint32_t local = 0;
+            for (int q = q0; q < q1; ++q)
+                local += cnt[q];
+            uint32_t incl = local;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t v = __shfl_up(incl, off);
+                if (lane >= off)
+                    incl += v;
+            }
+            uint32_t run = incl - local;
+            for (int q = q0; q < q1; ++q) {
+                const uint32_t v = cnt[q];
+                cnt[q] = run;
+                run += v;
+            }
+        }
+        __syncthreads();
+        // new list; ranks go to the idle ping-pong buffer before A_lx is overwritten
+        uint16_t *newlx = Zk[cur ^ 1];
+        for (int j = lane; j < zn; j += 64)
+            newlx[j] = (uint16_t)(cnt[A_lx[Zp[cur][j]]] + Zk[cur][j]);
+        __syncthreads();
+        for (int j = lane; j < zn; j += 64) {
+            A_sc[j] = Zs[cur][j];
+            A_lx[j] = newlx[j];
+            rec[(size_t)d * K + j] = (uint32_t)Zp[cur][j] | ((uint32_t)Zk[cur][j] << 16);
+        }
+        n = zn;
+        __syncthreads();
+    }
+
+    // rebuild the position vectors (ranks 1..|Q|), rows padded with 1
+    const int nw = a.NP >> 2;
+    for (int r = lane; r < n; r += 64) {
+        uint32_t wv[kMaxN / 4];
+#pragma unroll
+        for (int w = 0; w < kMaxN / 4; ++w)
+            wv[w] = 0x01010101u;
+        int pidx = r;
+        for (int d = N - 1; d >= 0; --d) {
+            const uint32_t e = rec[(size_t)d * K + pidx];
+            const uint32_t pk = (e >> 16) + 1u;
+            pidx = (int)(e & 0xffffu);
+#pragma unroll
+            for (int w = 0; w < kMaxN / 4; ++w)
+                if (w == (d >> 2))
+                    wv[w] = (wv[w] & ~(0xffu << ((d & 3) * 8))) | (pk << ((d & 3) * 8));
+        }
+        uint32_t *dst = (uint32_t *)(a.P + ((size_t)s * a.K + r) * a.NP);
+#pragma unroll
+        for (int w = 0; w < kMaxN / 4; ++w)
+            if (w < nw)
+                dst[w] = wv[w];
+    }
+}
+
+// ============================================================================
+// a3: yt = Q^H y on MFMA.  Real form of the complex product:
+//   [Re yt_d]   sum_m [ qr  qi ] [yr_m]
+//   [Im yt_d] =       [-qi  qr ] [yi_m]
+// A (2N x 2M) times B (2M x T) with v_mfma_f32_16x16x4_f32: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; it receives D[4(l/16)+v][l%16], v = 0..3.
+// ============================================================================
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+struct RotArgs {
+    const float2 *Qd;  // (S, M, N)
+    const float2 *y;   // (T, S, M)
+    float2 *yt;        // (T, S, N)
+    int S, M, N, T;
+};
+
+__global__ __launch_bounds__(64) void rotate_kernel(RotArgs a)
+{
+    const int s = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int M = a.M, N = a.N, T = a.T, S = a.S;
+    const float2 *Qs = a.Qd + (size_t)s * M * N;
+    const int rtiles = (2 * N + 15) / 16;
+    const int ksteps = (2 * M + 3) / 4;
+    const int ctiles = (T + 15) / 16;
+    float *yt = (float *)a.yt;
+    for (int ct = 0; ct < ctiles; ++ct) {
+        const int tt = ct * 16 + i16;
+        for (int rt = 0; rt < rtiles; ++rt) {
+            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+            const int row = rt * 16 + i16;
+            const int d = row >> 1, part = row & 1;
+            for (int ks = 0; ks < ksteps; ++ks) {
+                const int k = ks * 4 + kq;
+                const int m = k >> 1, cp = k & 1;
+                float av = 0.f, bv = 0.f;
+                if (m < M && d < N) {
+                    const float2 qv = Qs[(size_t)m * N + d];
+                    av = part == 0 ? (cp == 0 ? qv.x : qv.y) : (cp == 0 ? -qv.y : qv.x);
+                }
+                if (m < M && tt < T) {
+                    const float2 yv = a.y[((size_t)tt * S + s) * M + m];
+                    bv = cp == 0 ? yv.x : yv.y;
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int orow = rt * 16 + 4 * kq + v;
+                const int od = orow >> 1, opart = orow & 1;
+                if (od < N && tt < T)
+                    yt[(((size_t)tt * S + s) * N + od) * 2 + opart] = acc[v];
+            }
+        }
+    }
+}
+
+
+template <int MMAX>
+hipError_t sqrd_launch_t(const float2 *H, const SlotDev &sd, uint32_t *rh, uint32_t *rb, hipStream_t st)
+{
+    SqrdArgs a;
+    a.H = H;
+    a.S = sd.S;
+    a.M = sd.M;
+    a.N = sd.N;
+    a.delta = delta_of(sd.bits);
+    a.sd = sd;
+    a.roff_h = rh;
+    a.roff_b = rb;
+    const int grid = (sd.S + 1) / 2;
+    hipLaunchKernelGGL(sqrd_kernel<MMAX>, dim3(grid), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace dev
+
+using namespace dev;
+
+
+int nmax_bucket(int N)
+{
+    return N <= 8 ? 8 : N <= 16 ? 16 : N <= 24 ? 24 : 32;
+}
+
+bool posvec_rec_fits_lds(int N, int K)
+{
+    return posvec_lds_bytes(N, K, true) <= 64 * 1024;
+}
+
+size_t posvec_lds_bytes(int N, int K, bool rec_in_lds)
+{
+    size_t b = (size_t)K * 3 * sizeof(double);           // A_sc, Zs[2]
+    b += (size_t)((5 * K + 1) & ~1) * sizeof(uint16_t);  // A_lx, Zp[2], Zk[2]
+    b += (size_t)K * sizeof(uint32_t);                    // cnt
+    if (rec_in_lds)
+        b += (size_t)N * K * sizeof(uint32_t);
+    return b;
+}
+
+hipError_t launch_sqrd_q(const float2 *H, const SlotDev &sd, uint32_t *roff_h, uint32_t *roff_b,
+                         hipStream_t st)
+{
+    const int mm = ((sd.M + 3) / 4) * 4;
+    switch (mm) {
+    case 4: return sqrd_launch_t<4>(H, sd, roff_h, roff_b, st);
+    case 8: return sqrd_launch_t<8>(H, sd, roff_h, roff_b, st);
+    case 12: return sqrd_launch_t<12>(H, sd, roff_h, roff_b, st);
+    case 16: return sqrd_launch_t<16>(H, sd, roff_h, roff_b, st);
+    case 20: return sqrd_launch_t<20>(H, sd, roff_h, roff_b, st);
+    case 24: return sqrd_launch_t<24>(H, sd, roff_h, roff_b, st);
+    case 28: return sqrd_launch_t<28>(H, sd, roff_h, roff_b, st);
+    case 32: return sqrd_launch_t<32>(H, sd, roff_h, roff_b, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_posvec(const SlotDev &sd, hipStream_t st)
+{
+    PosArgs a;
+    a.w = sd.wd;
+    a.S = sd.S;
+    a.N = sd.N;
+    a.nq = 1 << sd.bits;
+    a.K = sd.K;
+    a.NP = sd.NP;
+    a.P = sd.P;
+    a.rec_g = sd.rec;
+    const bool in_lds = posvec_rec_fits_lds(sd.N, sd.K);
+    const size_t lds = posvec_lds_bytes(sd.N, sd.K, in_lds);
+    if (in_lds) {
+        hipLaunchKernelGGL(posvec_kernel<true>, dim3(sd.S), dim3(64), lds, st, a);
+    } else {
+        hipError_t e = hipFuncSetAttribute((const void *)posvec_kernel<false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(posvec_kernel<false>, dim3(sd.S), dim3(64), lds, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rotate(const SlotDev &sd, const float2 *y, int T, float2 *yt, hipStream_t st)
+{
+    RotArgs a;
+    a.Qd = sd.Qd;
+    a.y = y;
+    a.yt = yt;
+    a.S = sd.S;
+    a.M = sd.M;
+    a.N = sd.N;
+    a.T = T;
+    hipLaunchKernelGGL(rotate_kernel, dim3(sd.S), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace mpnl

@@ -1,0 +1,742 @@
+// Host runtime of the MPNL detection library: contexts, validation, a
+// budgeted device-memory pool, slot state and kernel sequencing.  Implements
+// the C ABI declared in include/mpnl.h.
+#include "mpnl.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+
+namespace {
+
+struct Block {
+    void *ptr = nullptr;
+    size_t size = 0;
+    bool free = false;
+    hipStream_t last_stream = nullptr;
+    hipEvent_t ev = nullptr;  // recorded on last_stream when released
+    bool ev_pending = false;
+};
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+struct mpnl_slot {
+    mpnl::SlotDev sd{};
+    uint32_t *roff_h = nullptr;
+    uint32_t *roff_b = nullptr;
+    int block = -1;
+    hipStream_t stream = nullptr;  // stream of the last work that used the slot
+};
+
+struct mpnl_ctx {
+    int device = 0;
+    size_t budget = 0;
+    size_t held = 0;
+    int last_hip = 0;
+    int precision = MPNL_PREC_FP32;
+    std::vector<Block> blocks;
+    std::vector<mpnl_slot *> slots;
+    void *pinned = nullptr;  // staging for batch job tables
+    size_t pinned_size = 0;
+    hipEvent_t pinned_ev = nullptr;
+    // kernel timers
+    bool prof = false;
+    struct Timed {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> spare_events;
+};
+
+namespace {
+
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev_) != hipSuccess)
+            prev_ = -1;
+        ok_ = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev_ >= 0)
+            (void)hipSetDevice(prev_);
+    }
+    bool ok() const { return ok_; }
+
+  private:
+    int prev_ = -1;
+    bool ok_ = false;
+};
+
+int hip_fail(mpnl_ctx *ctx, hipError_t e)
+{
+    ctx->last_hip = (int)e;
+    return e == hipErrorOutOfMemory ? MPNL_E_NOMEM : MPNL_E_HIP;
+}
+
+bool block_idle(const Block &b, hipStream_t st)
+{
+    if (!b.free)
+        return false;
+    if (!b.ev_pending || b.last_stream == st)
+        return true;
+    return hipEventQuery(b.ev) == hipSuccess;
+}
+
+// Device memory from the context pool.  A released block is reused at once on
+// the stream that released it (stream order protects it) and on other
+// streams only after the work enqueued before its release has finished.
+int pool_alloc(mpnl_ctx *ctx, size_t bytes, hipStream_t st, int *out_block)
+{
+    bytes = align_up(std::max<size_t>(bytes, 1));
+    int best = -1;
+    for (int i = 0; i < (int)ctx->blocks.size(); ++i) {
+        const Block &b = ctx->blocks[i];
+        if (b.size >= bytes && b.size <= 2 * bytes + (1u << 20) && block_idle(b, st)) {
+            if (best < 0 || b.size < ctx->blocks[best].size)
+                best = i;
+        }
+    }
+    if (best >= 0) {
+        ctx->blocks[best].free = false;
+        *out_block = best;
+        return MPNL_OK;
+    }
+    if (ctx->budget && ctx->held + bytes > ctx->budget) {
+        // give back idle cached blocks until the request fits
+        for (int i = 0; i < (int)ctx->blocks.size() && ctx->held + bytes > ctx->budget; ++i) {
+            Block &b = ctx->blocks[i];
+            if (b.ptr && b.free && (!b.ev_pending || hipEventQuery(b.ev) == hipSuccess)) {
+                (void)hipFree(b.ptr);
+                ctx->held -= b.size;
+                b.ptr = nullptr;
+                b.size = 0;
+            }
+        }
+        if (ctx->held + bytes > ctx->budget)
+            return MPNL_E_NOMEM;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e);
+    int slot = -1;
+    for (int i = 0; i < (int)ctx->blocks.size(); ++i)
+        if (ctx->blocks[i].ptr == nullptr && ctx->blocks[i].size == 0) {
+            slot = i;
+            break;
+        }
+    if (slot < 0) {
+        ctx->blocks.emplace_back();
+        slot = (int)ctx->blocks.size() - 1;
+        e = hipEventCreateWithFlags(&ctx->blocks[slot].ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipFree(p);
+            ctx->blocks.pop_back();
+            return hip_fail(ctx, e);
+        }
+    }
+    Block &b = ctx->blocks[slot];
+    b.ptr = p;
+    b.size = bytes;
+    b.free = false;
+    b.ev_pending = false;
+    ctx->held += bytes;
+    *out_block = slot;
+    return MPNL_OK;
+}
+
+void pool_release(mpnl_ctx *ctx, int blk, hipStream_t st)
+{
+    if (blk < 0 || blk >= (int)ctx->blocks.size())
+        return;
+    Block &b = ctx->blocks[blk];
+    b.free = true;
+    b.last_stream = st;
+    b.ev_pending = hipEventRecord(b.ev, st) == hipSuccess;
+}
+
+hipEvent_t take_event(mpnl_ctx *ctx)
+{
+    if (!ctx->spare_events.empty()) {
+        hipEvent_t e = ctx->spare_events.back();
+        ctx->spare_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+// Bracket one launch with timing events when the timers are on.
+class StageTimer {
+  public:
+    StageTimer(mpnl_ctx *ctx, int stage, hipStream_t st) : ctx_(ctx), stage_(stage), st_(st)
+    {
+        if (!ctx->prof)
+            return;
+        a_ = take_event(ctx);
+        b_ = take_event(ctx);
+        if (a_ && b_)
+            (void)hipEventRecord(a_, st_);
+    }
+    ~StageTimer()
+    {
+        if (!ctx_->prof || !a_ || !b_)
+            return;
+        (void)hipEventRecord(b_, st_);
+        ctx_->timed.push_back({stage_, a_, b_});
+    }
+
+  private:
+    mpnl_ctx *ctx_;
+    int stage_;
+    hipStream_t st_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+long long num_vectors_sat(int nq, int N)
+{
+    long long v = 1;
+    for (int i = 0; i < N; ++i) {
+        v *= nq;
+        if (v > (1LL << 40))
+            return 1LL << 40;
+    }
+    return v;
+}
+
+int validate_shape(int S, int M, int N, int mod, int n_paths)
+{
+    if (S <= 0 || M <= 0 || N <= 0 || n_paths < 1)
+        return MPNL_E_INVAL;
+    if (mod != MPNL_QPSK && mod != MPNL_QAM16 && mod != MPNL_QAM64)
+        return MPNL_E_UNSUPPORTED;
+    if (N > M || N > MPNL_MAX_USERS || M > MPNL_MAX_ANTENNAS)
+        return MPNL_E_UNSUPPORTED;
+    const long long K = std::min<long long>(n_paths, num_vectors_sat(1 << mod, N));
+    if (K > MPNL_MAX_PATHS)
+        return MPNL_E_UNSUPPORTED;
+    if ((long long)S * M * N > INT_MAX / 2)
+        return MPNL_E_UNSUPPORTED;
+    return MPNL_OK;
+}
+
+// Offsets of the slot arrays inside one pool block.
+struct SlotLayout {
+    size_t Qd, roff, roff_h, roff_b, diag, wd, permd, P, rec, total;
+};
+
+SlotLayout slot_layout(int S, int M, int N, int K, int NP, bool rec_global)
+{
+    SlotLayout L{};
+    size_t o = 0;
+    auto put = [&](size_t &field, size_t bytes) {
+        field = o;
+        o += align_up(bytes);
+    };
+    const size_t sNN = (size_t)S * N * N;
+    put(L.Qd, (size_t)S * M * N * sizeof(float2));
+    put(L.roff, sNN * sizeof(float2));
+    put(L.roff_h, sNN * sizeof(uint32_t));
+    put(L.roff_b, sNN * sizeof(uint32_t));
+    put(L.diag, (size_t)S * N * sizeof(float4));
+    put(L.wd, (size_t)S * N * sizeof(double));
+    put(L.permd, (size_t)S * N * sizeof(int32_t));
+    put(L.P, (size_t)S * K * NP);
+    put(L.rec, rec_global ? (size_t)S * N * K * sizeof(uint32_t) : 0);
+    L.total = o;
+    return L;
+}
+
+int prepare_impl(mpnl_ctx *ctx, const void *H, int S, int M, int N, int mod, int n_paths,
+                 hipStream_t st, mpnl_slot **out)
+{
+    const int K = (int)std::min<long long>(n_paths, num_vectors_sat(1 << mod, N));
+    const int NP = (N + 3) / 4 * 4;
+    const bool rec_global = !mpnl::posvec_rec_fits_lds(N, K);
+    const SlotLayout L = slot_layout(S, M, N, K, NP, rec_global);
+    int blk = -1;
+    int rc = pool_alloc(ctx, L.total, st, &blk);
+    if (rc != MPNL_OK)
+        return rc;
+    mpnl_slot *slot = new (std::nothrow) mpnl_slot();
+    if (!slot) {
+        pool_release(ctx, blk, st);
+        return MPNL_E_NOMEM;
+    }
+    char *base = (char *)ctx->blocks[blk].ptr;
+    mpnl::SlotDev &sd = slot->sd;
+    sd.S = S;
+    sd.M = M;
+    sd.N = N;
+    sd.bits = mod;
+    sd.K = K;
+    sd.NP = NP;
+    sd.Qd = (float2 *)(base + L.Qd);
+    sd.roff = (float2 *)(base + L.roff);
+    sd.diag = (float4 *)(base + L.diag);
+    sd.wd = (double *)(base + L.wd);
+    sd.permd = (int32_t *)(base + L.permd);
+    sd.P = (uint8_t *)(base + L.P);
+    sd.rec = rec_global ? (uint32_t *)(base + L.rec) : nullptr;
+    slot->roff_h = (uint32_t *)(base + L.roff_h);
+    slot->roff_b = (uint32_t *)(base + L.roff_b);
+    slot->block = blk;
+    slot->stream = st;
+    hipError_t e;
+    {
+        StageTimer tm(ctx, MPNL_STAGE_SQRD, st);
+        e = mpnl::launch_sqrd_q((const float2 *)H, sd, slot->roff_h, slot->roff_b, st);
+    }
+    if (e == hipSuccess) {
+        StageTimer tm(ctx, MPNL_STAGE_POSVEC, st);
+        e = mpnl::launch_posvec(sd, st);
+    }
+    if (e != hipSuccess) {
+        pool_release(ctx, blk, st);
+        delete slot;
+        return hip_fail(ctx, e);
+    }
+    ctx->slots.push_back(slot);
+    *out = slot;
+    return MPNL_OK;
+}
+
+void release_impl(mpnl_ctx *ctx, mpnl_slot *slot)
+{
+    pool_release(ctx, slot->block, slot->stream);
+    ctx->slots.erase(std::remove(ctx->slots.begin(), ctx->slots.end(), slot), ctx->slots.end());
+    delete slot;
+}
+
+bool owns(const mpnl_ctx *ctx, const mpnl_slot *slot)
+{
+    return std::find(ctx->slots.begin(), ctx->slots.end(), slot) != ctx->slots.end();
+}
+
+int detect_impl(mpnl_ctx *ctx, mpnl_slot *slot, const void *y, int T, int32_t *out, hipStream_t st,
+                bool soft, float sigma2, float clip, float *llr)
+{
+    const mpnl::SlotDev &sd = slot->sd;
+    if ((long long)sd.S * T > INT_MAX / 2)
+        return MPNL_E_UNSUPPORTED;
+    int blk = -1;
+    int rc = pool_alloc(ctx, (size_t)T * sd.S * sd.N * sizeof(float2), st, &blk);
+    if (rc != MPNL_OK)
+        return rc;
+    float2 *yt = (float2 *)ctx->blocks[blk].ptr;
+    hipError_t e;
+    {
+        StageTimer tm(ctx, MPNL_STAGE_ROTATE, st);
+        e = mpnl::launch_rotate(sd, (const float2 *)y, T, yt, st);
+    }
+    if (e == hipSuccess) {
+        StageTimer tm(ctx, MPNL_STAGE_PATHS, st);
+        if (soft) {
+            e = mpnl::launch_path_search_soft(sd, yt, T, sigma2, clip, llr, out, st);
+        } else {
+            const uint32_t *q = ctx->precision == MPNL_PREC_FP16   ? slot->roff_h
+                                : ctx->precision == MPNL_PREC_BF16 ? slot->roff_b
+                                                                   : nullptr;
+            e = mpnl::launch_path_search_q(sd, yt, T, out, ctx->precision, q, st);
+        }
+    }
+    pool_release(ctx, blk, st);
+    slot->stream = st;
+    if (e != hipSuccess)
+        return hip_fail(ctx, e);
+    return MPNL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpnl_create(mpnl_ctx **ctx, int device, size_t hbm_budget_bytes, unsigned flags)
+{
+    if (!ctx || flags != 0)
+        return MPNL_E_INVAL;
+    *ctx = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+        return MPNL_E_HIP;
+    mpnl_ctx *c = new (std::nothrow) mpnl_ctx();
+    if (!c)
+        return MPNL_E_NOMEM;
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    *ctx = c;
+    return MPNL_OK;
+}
+
+int mpnl_destroy(mpnl_ctx *ctx)
+{
+    if (!ctx)
+        return MPNL_OK;
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (mpnl_slot *s : ctx->slots)
+        delete s;
+    for (Block &b : ctx->blocks) {
+        if (b.ptr)
+            (void)hipFree(b.ptr);
+        if (b.ev)
+            (void)hipEventDestroy(b.ev);
+    }
+    if (ctx->pinned)
+        (void)hipHostFree(ctx->pinned);
+    if (ctx->pinned_ev)
+        (void)hipEventDestroy(ctx->pinned_ev);
+    for (auto &t : ctx->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (hipEvent_t e : ctx->spare_events)
+        (void)hipEventDestroy(e);
+    delete ctx;
+    return MPNL_OK;
+}
+
+const char *mpnl_strerror(int code)
+{
+    switch (code) {
+    case MPNL_OK: return "success";
+    case MPNL_E_INVAL: return "invalid argument (null pointer, non-positive size or n_paths < 1)";
+    case MPNL_E_UNSUPPORTED: return "unsupported shape or modulation (N > M, N or M > 32, unknown modulation, too many paths)";
+    case MPNL_E_NOMEM: return "device memory budget exceeded";
+    case MPNL_E_HIP: return "HIP runtime error (see mpnl_last_hip_error)";
+    default: return "unknown error code";
+    }
+}
+
+int mpnl_last_hip_error(const mpnl_ctx *ctx) { return ctx ? ctx->last_hip : 0; }
+
+int mpnl_set_precision(mpnl_ctx *ctx, int precision)
+{
+    if (!ctx || precision < MPNL_PREC_FP32 || precision > MPNL_PREC_BF16)
+        return MPNL_E_INVAL;
+    ctx->precision = precision;
+    return MPNL_OK;
+}
+
+int mpnl_profile_enable(mpnl_ctx *ctx, int enable)
+{
+    if (!ctx)
+        return MPNL_E_INVAL;
+    ctx->prof = enable != 0;
+    return MPNL_OK;
+}
+
+int mpnl_profile_collect(mpnl_ctx *ctx, double *total_ms, int *launches)
+{
+    if (!ctx)
+        return MPNL_E_INVAL;
+    DeviceGuard g(ctx->device);
+    double ms[MPNL_NUM_STAGES] = {0, 0, 0, 0};
+    int cnt[MPNL_NUM_STAGES] = {0, 0, 0, 0};
+    hipError_t err = hipSuccess;
+    for (auto &t : ctx->timed) {
+        float x = 0.f;
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&x, t.a, t.b);
+        if (e != hipSuccess)
+            err = e;
+        else if (t.stage >= 0 && t.stage < MPNL_NUM_STAGES) {
+            ms[t.stage] += x;
+            cnt[t.stage] += 1;
+        }
+        ctx->spare_events.push_back(t.a);
+        ctx->spare_events.push_back(t.b);
+    }
+    ctx->timed.clear();
+    for (int i = 0; i < MPNL_NUM_STAGES; ++i) {
+        if (total_ms)
+            total_ms[i] = ms[i];
+        if (launches)
+            launches[i] = cnt[i];
+    }
+    if (err != hipSuccess)
+        return hip_fail(ctx, err);
+    return MPNL_OK;
+}
+
+int mpnl_memory_usage(const mpnl_ctx *ctx, size_t *held, size_t *in_use)
+{
+    if (!ctx)
+        return MPNL_E_INVAL;
+    size_t used = 0;
+    for (const Block &b : ctx->blocks)
+        if (b.ptr && !b.free)
+            used += b.size;
+    if (held)
+        *held = ctx->held;
+    if (in_use)
+        *in_use = used;
+    return MPNL_OK;
+}
+
+int mpnl_slot_prepare(mpnl_ctx *ctx, const void *H, int S, int M, int N, int mod, int n_paths,
+                      void *stream, mpnl_slot **slot)
+{
+    if (!ctx || !H || !slot)
+        return MPNL_E_INVAL;
+    *slot = nullptr;
+    int rc = validate_shape(S, M, N, mod, n_paths);
+    if (rc != MPNL_OK)
+        return rc;
+    DeviceGuard g(ctx->device);
+    if (!g.ok())
+        return hip_fail(ctx, hipErrorInvalidDevice);
+    return prepare_impl(ctx, H, S, M, N, mod, n_paths, (hipStream_t)stream, slot);
+}
+
+int mpnl_slot_detect(mpnl_ctx *ctx, mpnl_slot *slot, const void *y, int T, int32_t *out, void *stream)
+{
+    if (!ctx || !slot || !y || !out || T <= 0 || !owns(ctx, slot))
+        return MPNL_E_INVAL;
+    DeviceGuard g(ctx->device);
+    if (!g.ok())
+        return hip_fail(ctx, hipErrorInvalidDevice);
+    return detect_impl(ctx, slot, y, T, out, (hipStream_t)stream, false, 0.f, 0.f, nullptr);
+}
+
+int mpnl_slot_detect_soft(mpnl_ctx *ctx, mpnl_slot *slot, const void *y, int T, float sigma2,
+                          float clip, float *llr, int32_t *out, void *stream)
+{
+    if (!ctx || !slot || !y || !llr || T <= 0 || !owns(ctx, slot) || !(sigma2 > 0.f) ||
+        !(clip > 0.f))
+        return MPNL_E_INVAL;
+    DeviceGuard g(ctx->device);
+    if (!g.ok())
+        return hip_fail(ctx, hipErrorInvalidDevice);
+    return detect_impl(ctx, slot, y, T, out, (hipStream_t)stream, true, sigma2, clip, llr);
+}
+
+int mpnl_slot_release(mpnl_ctx *ctx, mpnl_slot *slot)
+{
+    if (!slot)
+        return MPNL_OK;
+    if (!ctx || !owns(ctx, slot))
+        return MPNL_E_INVAL;
+    DeviceGuard g(ctx->device);
+    release_impl(ctx, slot);
+    return MPNL_OK;
+}
+
+int mpnl_slot_info(const mpnl_slot *slot, int *S, int *M, int *N, int *mod, int *K)
+{
+    if (!slot)
+        return MPNL_E_INVAL;
+    if (S) *S = slot->sd.S;
+    if (M) *M = slot->sd.M;
+    if (N) *N = slot->sd.N;
+    if (mod) *mod = slot->sd.bits;
+    if (K) *K = slot->sd.K;
+    return MPNL_OK;
+}
+
+int mpnl_slot_export(mpnl_ctx *ctx, const mpnl_slot *slot, int32_t *perm, double *w, void *roff,
+                     uint8_t *P, void *stream)
+{
+    if (!ctx || !slot || !owns(ctx, slot))
+        return MPNL_E_INVAL;
+    DeviceGuard g(ctx->device);
+    const mpnl::SlotDev &sd = slot->sd;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    const size_t SN = (size_t)sd.S * sd.N;
+    if (perm && e == hipSuccess)
+        e = hipMemcpyAsync(perm, sd.permd, SN * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+    if (w && e == hipSuccess)
+        e = hipMemcpyAsync(w, sd.wd, SN * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (roff && e == hipSuccess)
+        e = hipMemcpyAsync(roff, sd.roff, SN * sd.N * sizeof(float2), hipMemcpyDeviceToDevice, st);
+    if (P && e == hipSuccess)
+        e = hipMemcpy2DAsync(P, sd.N, sd.P, sd.NP, sd.N, (size_t)sd.S * sd.K, hipMemcpyDeviceToDevice,
+                             st);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e);
+    return MPNL_OK;
+}
+
+int mpnl_detect(mpnl_ctx *ctx, const void *H, const void *y, int S, int T, int M, int N, int mod,
+                int n_paths, int32_t *out, void *stream)
+{
+    if (!ctx || !H || !y || !out || T <= 0)
+        return MPNL_E_INVAL;
+    int rc = validate_shape(S, M, N, mod, n_paths);
+    if (rc != MPNL_OK)
+        return rc;
+    DeviceGuard g(ctx->device);
+    if (!g.ok())
+        return hip_fail(ctx, hipErrorInvalidDevice);
+    hipStream_t st = (hipStream_t)stream;
+    mpnl_slot *slot = nullptr;
+    rc = prepare_impl(ctx, H, S, M, N, mod, n_paths, st, &slot);
+    if (rc != MPNL_OK)
+        return rc;
+    rc = detect_impl(ctx, slot, y, T, out, st, false, 0.f, 0.f, nullptr);
+    release_impl(ctx, slot);
+    return rc;
+}
+
+int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *stream)
+{
+    if (!ctx || !jobs || n_jobs <= 0)
+        return MPNL_E_INVAL;
+    for (int i = 0; i < n_jobs; ++i) {
+        const mpnl_job &j = jobs[i];
+        if (!j.H || !j.y || !j.out || j.T <= 0)
+            return MPNL_E_INVAL;
+        int rc = validate_shape(j.S, j.M, j.N, j.mod, j.n_paths);
+        if (rc != MPNL_OK)
+            return rc;
+        if ((long long)j.S * j.T > INT_MAX / 4)
+            return MPNL_E_UNSUPPORTED;
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok())
+        return hip_fail(ctx, hipErrorInvalidDevice);
+    hipStream_t st = (hipStream_t)stream;
+
+    // a1-a3 per job
+    std::vector<mpnl_slot *> slots(n_jobs, nullptr);
+    std::vector<int> ytb(n_jobs, -1);
+    int rc = MPNL_OK;
+    for (int i = 0; i < n_jobs && rc == MPNL_OK; ++i) {
+        const mpnl_job &j = jobs[i];
+        rc = prepare_impl(ctx, j.H, j.S, j.M, j.N, j.mod, j.n_paths, st, &slots[i]);
+        if (rc != MPNL_OK)
+            break;
+        rc = pool_alloc(ctx, (size_t)j.T * j.S * j.N * sizeof(float2), st, &ytb[i]);
+        if (rc != MPNL_OK)
+            break;
+        hipError_t e;
+        {
+            StageTimer tm(ctx, MPNL_STAGE_ROTATE, st);
+            e = mpnl::launch_rotate(slots[i]->sd, (const float2 *)j.y, j.T,
+                                    (float2 *)ctx->blocks[ytb[i]].ptr, st);
+        }
+        if (e != hipSuccess)
+            rc = hip_fail(ctx, e);
+    }
+
+    // a4+a5: one persistent launch per (user-count bucket, modulation)
+    if (rc == MPNL_OK) {
+        struct Group {
+            int bucket, bits;
+            std::vector<int> idx;
+        };
+        std::vector<Group> groups;
+        for (int i = 0; i < n_jobs; ++i) {
+            const int bk = mpnl::nmax_bucket(jobs[i].N), bits = jobs[i].mod;
+            auto it = std::find_if(groups.begin(), groups.end(),
+                                   [&](const Group &q) { return q.bucket == bk && q.bits == bits; });
+            if (it == groups.end()) {
+                groups.push_back({bk, bits, {}});
+                it = groups.end() - 1;
+            }
+            it->idx.push_back(i);
+        }
+        // job tables of every group, plus one queue counter per group, in one upload
+        size_t table_bytes = 0;
+        std::vector<size_t> goff(groups.size());
+        for (size_t q = 0; q < groups.size(); ++q) {
+            goff[q] = table_bytes;
+            table_bytes += align_up(groups[q].idx.size() * sizeof(mpnl::JobDev) + sizeof(unsigned) * 4);
+        }
+        if (ctx->pinned_ev && hipEventSynchronize(ctx->pinned_ev) != hipSuccess)
+            rc = MPNL_E_HIP;
+        if (rc == MPNL_OK && ctx->pinned_size < table_bytes) {
+            if (ctx->pinned)
+                (void)hipHostFree(ctx->pinned);
+            ctx->pinned = nullptr;
+            ctx->pinned_size = 0;
+            hipError_t e = hipHostMalloc(&ctx->pinned, table_bytes, hipHostMallocDefault);
+            if (e != hipSuccess)
+                rc = hip_fail(ctx, e);
+            else
+                ctx->pinned_size = table_bytes;
+        }
+        if (rc == MPNL_OK && !ctx->pinned_ev) {
+            hipError_t e = hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming);
+            if (e != hipSuccess)
+                rc = hip_fail(ctx, e);
+        }
+        int tblk = -1;
+        if (rc == MPNL_OK)
+            rc = pool_alloc(ctx, table_bytes, st, &tblk);
+        if (rc == MPNL_OK) {
+            char *host = (char *)ctx->pinned;
+            char *dev = (char *)ctx->blocks[tblk].ptr;
+            std::vector<int> items(groups.size()), threads(groups.size());
+            for (size_t q = 0; q < groups.size(); ++q) {
+                mpnl::JobDev *jd = (mpnl::JobDev *)(host + goff[q]);
+                int acc = 0, thr = 64;
+                for (size_t u = 0; u < groups[q].idx.size(); ++u) {
+                    const int i = groups[q].idx[u];
+                    const mpnl::SlotDev &sd = slots[i]->sd;
+                    mpnl::JobDev &J = jd[u];
+                    J.yt = (const float2 *)ctx->blocks[ytb[i]].ptr;
+                    J.roff = sd.roff;
+                    J.diag = sd.diag;
+                    J.permd = sd.permd;
+                    J.P = sd.P;
+                    J.out = jobs[i].out;
+                    J.S = sd.S;
+                    J.T = jobs[i].T;
+                    J.N = sd.N;
+                    J.K = sd.K;
+                    J.NP = sd.NP;
+                    J.item_begin = acc;
+                    acc += sd.S * jobs[i].T;
+                    thr = std::max(thr, sd.K >= 256 ? 256 : (sd.K + 63) / 64 * 64);
+                }
+                unsigned *cnt = (unsigned *)(host + goff[q] + groups[q].idx.size() * sizeof(mpnl::JobDev));
+                cnt[0] = 0;
+                items[q] = acc;
+                threads[q] = thr;
+            }
+            hipError_t e = hipMemcpyAsync(dev, host, table_bytes, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess)
+                e = hipEventRecord(ctx->pinned_ev, st);
+            for (size_t q = 0; q < groups.size() && e == hipSuccess; ++q) {
+                const mpnl::JobDev *jd = (const mpnl::JobDev *)(dev + goff[q]);
+                unsigned *cnt = (unsigned *)(dev + goff[q] + groups[q].idx.size() * sizeof(mpnl::JobDev));
+                // enough resident workgroups to fill the 256 CUs, never more than the items
+                const int grid = std::min(items[q], 256 * (threads[q] >= 256 ? 4 : 8));
+                StageTimer tm(ctx, MPNL_STAGE_PATHS, st);
+                e = mpnl::launch_path_search_batch(jd, (int)groups[q].idx.size(), items[q], groups[q].bucket,
+                                                   groups[q].bits, threads[q], cnt, grid, st);
+            }
+            if (e != hipSuccess)
+                rc = hip_fail(ctx, e);
+            pool_release(ctx, tblk, st);
+        }
+    }
+    for (int i = 0; i < n_jobs; ++i) {
+        if (ytb[i] >= 0)
+            pool_release(ctx, ytb[i], st);
+        if (slots[i])
+            release_impl(ctx, slots[i]);
+    }
+    return rc;
+}
+
+}  // extern "C"

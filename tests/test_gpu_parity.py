@@ -1,0 +1,326 @@
+"""GPU parity of the MPNL hot path against the FP64 oracle, through the C ABI.
+
+Every case prints its name, shape and seed before touching the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity_util import TOL, classify
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import paper_2409_14355_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mp):
+    c = mp.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def _run(ctx, sl, n_paths):
+    out = ctx.detect(_dev(sl.H), _dev(sl.y), sl.bits, n_paths)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _assert_parity(sl, got, n_paths, nthreads=8, label=""):
+    ref, diag = oracle.detect_slot("mpnl", sl.H, sl.y, sl.bits, n_paths=n_paths,
+                                   want_diag=True, nthreads=nthreads)
+    n_bad, counts, unexplained = classify(sl.H, sl.y, got, ref, diag, sl.bits)
+    print(f"{label}: {n_bad} of {ref.shape[0] * ref.shape[1]} vectors differ; classes {counts}",
+          flush=True)
+    assert not unexplained, unexplained[:3]
+    return ref, n_bad
+
+
+# ------------------------------------------------------------------ a1 / a2 ---
+@pytest.mark.parametrize("S,M,N,bits,ch", [(37, 4, 4, 2, "iid"), (16, 16, 16, 4, "iid"),
+                                           (9, 24, 24, 4, "kron"), (11, 32, 12, 6, "iid"),
+                                           (5, 7, 3, 4, "iid"), (4, 32, 32, 6, "iid")])
+def test_sorted_qr_stage(ctx, S, M, N, bits, ch):
+    _say("sqrd", S, M, N, bits, ch)
+    sl = synth.make_slot(S=S, T=1, M=M, N=N, bits=bits, snr_db=18, seed=(201, S, M, N), channel=ch,
+                         rho_rx=0.5, rho_tx=0.3)
+    slot = ctx.slot_prepare(_dev(sl.H), bits, 64)
+    ex = slot.export()
+    torch.cuda.synchronize()
+    perm = ex["perm"].cpu().numpy()
+    w = ex["w"].cpu().numpy()
+    roff = ex["roff"].cpu().numpy()
+    slot.release()
+    for s in range(S):
+        Q, R, operm, pm = oracle.sqrd(sl.H[s])
+        operm_d = operm[::-1]          # depth order
+        if not np.array_equal(perm[s], operm_d):
+            assert pm < TOL, (s, perm[s], operm_d, pm)
+            continue
+        rd = np.real(np.diag(R))[::-1]
+        scale = np.abs(sl.H[s]).max()
+        assert np.allclose(np.sqrt(w[s]), rd, rtol=1e-5, atol=1e-5 * scale)
+        for d in range(N):
+            for d2 in range(d + 1, N):
+                ref = R[N - 1 - d2, N - 1 - d]
+                assert abs(roff[s, d, d2] - ref) < 2e-5 * max(1.0, scale * math.sqrt(M)), (s, d, d2)
+
+
+@pytest.mark.parametrize("S,M,N,bits,K", [(20, 4, 4, 2, 16), (12, 16, 16, 4, 256), (6, 24, 24, 4, 256),
+                                          (8, 8, 8, 6, 128), (4, 3, 3, 4, 4096), (6, 12, 10, 4, 1000),
+                                          (5, 4, 2, 6, 4096), (7, 6, 5, 2, 100)])
+def test_position_set_stage(ctx, S, M, N, bits, K):
+    """a2 on the GPU's own float64 weights equals the oracle's best-first set."""
+    _say("posvec", S, M, N, bits, K)
+    sl = synth.make_slot(S=S, T=1, M=M, N=N, bits=bits, snr_db=15, seed=(202, S, N, K))
+    slot = ctx.slot_prepare(_dev(sl.H), bits, K)
+    ex = slot.export()
+    torch.cuda.synchronize()
+    w = ex["w"].cpu().numpy()
+    P = ex["P"].cpu().numpy()
+    slot.release()
+    for s in range(S):
+        Pr, _, bmargin = oracle.position_set(w[s], 1 << bits, K)
+        assert P.shape[1] == Pr.shape[0]
+        if not np.array_equal(P[s], Pr):
+            # only a rounding tie in the score may reorder the set
+            assert set(map(tuple, P[s].tolist())) == set(map(tuple, Pr.tolist())) or bmargin < 1e-12, s
+
+
+# ------------------------------------------------------------- end to end ---
+CASES = [
+    # name, S, T, M, N, bits, snr, K, channel
+    ("4x4-qpsk-S64-T1-K16", 64, 1, 4, 4, 2, 10, 16, "iid"),
+    ("16x16-qam16-K64", 40, 14, 16, 16, 4, 14, 64, "iid"),
+    ("16x16-qam16-K256", 24, 14, 16, 16, 4, 20, 256, "iid"),
+    ("24x24-qam16-kron-K256", 12, 14, 24, 24, 4, 18, 256, "kron"),
+    ("8x8-qam64-K128", 30, 5, 8, 8, 6, 22, 128, "iid"),
+    ("32x12-qam64-K256", 10, 3, 32, 12, 6, 20, 256, "iid"),
+    ("32x32-qpsk-K64", 6, 2, 32, 32, 2, 8, 64, "iid"),
+    ("6x5-qam16-K1000", 9, 17, 6, 5, 4, 12, 1000, "iid"),
+    ("3x1-qam64-K8", 33, 3, 3, 1, 6, 15, 8, "iid"),
+    ("7x3-qpsk-K100-odd", 15, 2, 7, 3, 2, 5, 100, "iid"),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_detect_parity(ctx, case):
+    name, S, T, M, N, bits, snr, K, ch = case
+    _say("detect", name)
+    sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=snr, seed=(203, S, T, M, N, K),
+                         channel=ch, rho_rx=0.5, rho_tx=0.3)
+    got = _run(ctx, sl, K)
+    assert got.min() >= 0 and got.max() < (1 << bits)
+    _assert_parity(sl, got, K, label=name)
+
+
+@pytest.mark.parametrize("M,N,bits,S", [(4, 4, 2, 40), (3, 3, 4, 12), (2, 2, 6, 24), (6, 4, 2, 30)])
+def test_enough_paths_is_ml(ctx, M, N, bits, S):
+    """With N_p >= |Q|^N the detector is exact ML (clamped path count)."""
+    _say("ml", M, N, bits, S)
+    sl = synth.make_slot(S=S, T=2, M=M, N=N, bits=bits, snr_db=6, seed=(204, M, N, bits))
+    got = _run(ctx, sl, 10 ** 6)
+    ref = oracle.detect_slot("ml", sl.H, sl.y, bits, nthreads=8)
+    mism = np.any(got != ref, axis=-1)
+    for t, s in zip(*np.nonzero(mism)):
+        r_got = oracle.residual_norm2(sl.H[s], sl.y[t, s], bits, got[t, s])
+        r_ref = oracle.residual_norm2(sl.H[s], sl.y[t, s], bits, ref[t, s])
+        assert abs(r_got - r_ref) <= TOL * r_ref, (t, s)
+
+
+def test_noise_free_and_one_path(ctx):
+    _say("noise-free")
+    sl = synth.make_slot(S=50, T=3, M=10, N=8, bits=4, snr_db=0, seed=(205,), noise=False)
+    got = _run(ctx, sl, 1)
+    assert np.array_equal(got, sl.s_idx)
+
+
+def test_zero_column_channel(ctx):
+    _say("zero-column")
+    sl = synth.make_slot(S=20, T=2, M=6, N=4, bits=4, snr_db=12, seed=(206,))
+    sl.H[:, :, 2] = 0
+    sl.y[...] = np.einsum("smn,tsn->tsm", sl.H.astype(np.complex128),
+                          synth._tx_points(4)[sl.s_idx]).astype(np.complex64) + sl.y * 0.01
+    got = _run(ctx, sl, 64)
+    _assert_parity(sl, got, 64, label="zero-column")
+    assert np.all(got[:, :, 2] == 0)
+
+
+def test_full_size_sampled_24x24_kron(ctx):
+    """24x24 16-QAM Kronecker slot of 3276 subcarriers x 14 symbols, 256 paths,
+    in the launch configuration the benchmark times; the oracle checks a sample."""
+    _say("full-size 24x24 S3276 T14 K256")
+    S, T, M, N, bits, K = 3276, 14, 24, 24, 4, 256
+    sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=18, seed=(3, 0, 0, 0), channel="kron",
+                         rho_rx=0.5, rho_tx=0.3)
+    got = _run(ctx, sl, K)
+    rng = np.random.default_rng(0)
+    sub = np.sort(rng.choice(S, size=24, replace=False))
+    sub_sl = synth.Slot(H=sl.H[sub], y=sl.y[:, sub], s_idx=sl.s_idx[:, sub], sigma2=sl.sigma2, bits=bits)
+    _assert_parity(sub_sl, got[:, sub], K, nthreads=16, label="24x24 kron S3276 T14 sample")
+
+
+def test_full_size_sampled_16x16(ctx):
+    _say("full-size 16x16 S1200 T14 K256")
+    S, T, M, N, bits, K = 1200, 14, 16, 16, 4, 256
+    sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=16, seed=(2, 3, 0, 0))
+    got = _run(ctx, sl, K)
+    sub = np.arange(0, S, 60)
+    sub_sl = synth.Slot(H=sl.H[sub], y=sl.y[:, sub], s_idx=sl.s_idx[:, sub], sigma2=sl.sigma2, bits=bits)
+    _assert_parity(sub_sl, got[:, sub], K, nthreads=16, label="16x16 S1200 T14 sample")
+
+
+def test_paired_ber_matches_oracle(ctx):
+    """BER of the GPU and of the FP64 oracle on the same samples agree within
+    the Wilson interval."""
+    _say("paired BER")
+    S, T, M, N, bits, K = 60, 14, 16, 16, 4, 64
+    sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=6, seed=(207,))
+    got = _run(ctx, sl, K)
+    ref = oracle.detect_slot("mpnl", sl.H, sl.y, bits, n_paths=K, nthreads=16)
+    n = sl.s_idx.size * bits
+    e_gpu = synth.bit_errors(got, sl.s_idx, bits)
+    e_ref = synth.bit_errors(ref, sl.s_idx, bits)
+    assert e_ref >= 100
+    lo, hi = synth.wilson(e_ref, n)
+    assert lo <= e_gpu / n <= hi
+
+
+# ---------------------------------------------------------- API behaviour ---
+def test_slot_reuse_equals_one_shot(ctx):
+    _say("slot reuse")
+    sl = synth.make_slot(S=30, T=14, M=12, N=10, bits=4, snr_db=14, seed=(208,))
+    sl2 = synth.make_slot(S=30, T=5, M=12, N=10, bits=4, snr_db=14, seed=(209,))
+    Hd = _dev(sl.H)
+    slot = ctx.slot_prepare(Hd, 4, 128)
+    a = slot.detect(_dev(sl.y))
+    y2 = _dev(sl2.y)
+    b = slot.detect(y2)
+    torch.cuda.synchronize()
+    one = ctx.detect(Hd, _dev(sl.y), 4, 128)
+    two = ctx.detect(Hd, y2, 4, 128)
+    torch.cuda.synchronize()
+    slot.release()
+    assert torch.equal(a, one) and torch.equal(b, two)
+
+
+def test_deterministic_and_batch_equals_alone(ctx):
+    _say("batch vs alone")
+    shapes = [(120, 14, 8, 6, 2, 64), (75, 14, 16, 16, 4, 128), (40, 14, 32, 20, 6, 256),
+              (33, 3, 5, 5, 4, 256), (64, 14, 12, 12, 4, 64)]
+    jobs, alone = [], []
+    for i, (S, T, M, N, bits, K) in enumerate(shapes):
+        sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=20, seed=(210, i))
+        H, y = _dev(sl.H), _dev(sl.y)
+        jobs.append(dict(H=H, y=y, mod=bits, n_paths=K, out=None))
+        a1 = ctx.detect(H, y, bits, K)
+        a2 = ctx.detect(H, y, bits, K)
+        torch.cuda.synchronize()
+        assert torch.equal(a1, a2)
+        alone.append(a1)
+    outs = ctx.detect_batch(jobs)
+    torch.cuda.synchronize()
+    for a, b in zip(alone, outs):
+        assert torch.equal(a, b)
+
+
+def test_error_codes(ctx, mp):
+    _say("error codes")
+    H = torch.zeros((4, 4, 4), dtype=torch.complex64, device="cuda:0")
+    y = torch.zeros((1, 4, 4), dtype=torch.complex64, device="cuda:0")
+    out = torch.zeros((1, 4, 4), dtype=torch.int32, device="cuda:0")
+    h = ctx.handle
+    L = mp.lib()
+    assert L.mpnl_detect(h, None, y.data_ptr(), 4, 1, 4, 4, 2, 16, out.data_ptr(), None) == mp.MPNL_E_INVAL
+    assert L.mpnl_detect(h, H.data_ptr(), y.data_ptr(), 0, 1, 4, 4, 2, 16, out.data_ptr(), None) == mp.MPNL_E_INVAL
+    assert L.mpnl_detect(h, H.data_ptr(), y.data_ptr(), 4, 1, 4, 4, 2, 0, out.data_ptr(), None) == mp.MPNL_E_INVAL
+    assert L.mpnl_detect(h, H.data_ptr(), y.data_ptr(), 4, 1, 4, 4, 3, 16, out.data_ptr(), None) == mp.MPNL_E_UNSUPPORTED
+    assert L.mpnl_detect(h, H.data_ptr(), y.data_ptr(), 4, 1, 3, 4, 2, 16, out.data_ptr(), None) == mp.MPNL_E_UNSUPPORTED
+    assert L.mpnl_detect(h, H.data_ptr(), y.data_ptr(), 4, 1, 40, 33, 2, 16, out.data_ptr(), None) == mp.MPNL_E_UNSUPPORTED
+    assert L.mpnl_detect(h, H.data_ptr(), y.data_ptr(), 4, 1, 8, 8, 4, 5000, out.data_ptr(), None) == mp.MPNL_E_UNSUPPORTED
+    assert L.mpnl_set_precision(h, 7) == mp.MPNL_E_INVAL
+    assert L.mpnl_slot_release(h, 12345) == mp.MPNL_E_INVAL
+
+
+def test_hbm_budget_admission(mp):
+    _say("budget")
+    small = mp.Context(0, hbm_budget_bytes=1 << 20)
+    sl = synth.make_slot(S=3000, T=14, M=24, N=24, bits=4, snr_db=18, seed=(211,))
+    with pytest.raises(mp.MpnlError) as ei:
+        small.slot_prepare(_dev(sl.H), 4, 256)
+    assert ei.value.code == mp.MPNL_E_NOMEM
+    sl2 = synth.make_slot(S=4, T=1, M=4, N=4, bits=2, snr_db=18, seed=(212,))
+    s2 = small.slot_prepare(_dev(sl2.H), 2, 16)
+    held, used = small.memory_usage()
+    assert 0 < used <= held <= (1 << 20)
+    s2.release()
+    small.close()
+
+
+# --------------------------------------------------------- precision ---
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp16", "bf16"])
+def test_reduced_precision_close_to_fp64(ctx, mp, prec):
+    """FP16 / BF16 path-metric operands with FP32 accumulation: the decision
+    mismatch against the FP64 oracle stays small and the BER stays inside the
+    oracle's Wilson interval."""
+    _say("precision", prec)
+    S, T, M, N, bits, K = 40, 14, 24, 24, 4, 256
+    sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=8, seed=(213,), channel="kron",
+                         rho_rx=0.5, rho_tx=0.3)
+    ctx.set_precision(prec)
+    try:
+        got = _run(ctx, sl, K)
+    finally:
+        ctx.set_precision(0)
+    ref = oracle.detect_slot("mpnl", sl.H, sl.y, bits, n_paths=K, nthreads=16)
+    frac = np.mean(np.any(got != ref, axis=-1))
+    n = sl.s_idx.size * bits
+    e_gpu, e_ref = synth.bit_errors(got, sl.s_idx, bits), synth.bit_errors(ref, sl.s_idx, bits)
+    lo, hi = synth.wilson(e_ref, n)
+    print(f"prec {prec}: vector mismatch {frac:.4f}, BER gpu {e_gpu / n:.3e} oracle {e_ref / n:.3e}",
+          flush=True)
+    assert frac < 0.05
+    assert lo <= e_gpu / n <= hi or abs(e_gpu - e_ref) <= 3 * math.sqrt(max(e_ref, 1))
+
+
+# ---------------------------------------------------------- soft output ---
+def test_soft_output_matches_oracle(ctx):
+    _say("soft")
+    S, T, M, N, bits, K = 12, 3, 6, 4, 4, 64
+    sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=10, seed=(214,))
+    slot = ctx.slot_prepare(_dev(sl.H), bits, K)
+    out = torch.empty((T, S, N), dtype=torch.int32, device="cuda:0")
+    llr = slot.detect_soft(_dev(sl.y), sl.sigma2, 50.0, out=out)
+    torch.cuda.synchronize()
+    slot.release()
+    llr = llr.cpu().numpy()
+    got = out.cpu().numpy()
+    ref, diag = oracle.detect_slot("mpnl", sl.H, sl.y, bits, n_paths=K, want_diag=True)
+    n_bad, _, unexplained = classify(sl.H, sl.y, got, ref, diag, bits)
+    assert not unexplained
+    for s in range(S):
+        Q, R, perm, _ = oracle.sqrd(sl.H[s])
+        P, _, _ = oracle.position_set(oracle.depth_weights(R), 1 << bits, K)
+        for t in range(T):
+            r = oracle.mpnl_vector(Q, R, perm, P, sl.y[t, s], bits)
+            ol = oracle.llr_from_paths(r["metrics"], r["paths"], bits, sl.sigma2, 50.0)
+            if r["kth_margin"] < TOL:
+                continue
+            assert np.allclose(llr[t, s], ol, rtol=1e-3, atol=2e-3 * max(1.0, np.abs(ol).max())), (t, s)
