@@ -1,5 +1,18 @@
-// Device code shared by the kernel translation units of the MPNL library
-// (helpers, the a4 point choice and the path-search kernel templates).
+// Device code shared by the kernel translation units of the MPNL library:
+// helpers, the a4 point choice and the a4 + a5 path-search kernel templates.
+//
+// Lattice units.  On row l the residual b_l is kept divided by
+// a_l = R_ll * Delta, so every constellation level of an axis sits on an odd
+// integer -(L-1) .. L-1 and the distance of point c is
+//     |b_l - R_ll c|^2 = a_l^2 ((z_I - c_I)^2 + (z_Q - c_Q)^2),   z = b_l / a_l.
+// The sorted QR writes R already scaled this way (R'[d][e] = R_{l_e,l_d}
+// Delta / a_{l_e}) and the rotation writes yt / a_l, so the descent needs
+// no division: the nearest level is a round and a clamp.
+// Rows with R_ll = 0 keep scale 1 and are handled by index order.
+//
+// Uniform data (R, yt, the per-depth diagonal) are read through the constant
+// address space: the same address in every lane becomes a scalar load, and
+// the values feed the VALU as SGPR operands.
 #pragma once
 #include "kernels.h"
 
@@ -14,6 +27,17 @@ constexpr int kMaxN = 32;
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 typedef __bf16 bf162_t __attribute__((ext_vector_type(2)));
+
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+// Uniform arrays are read as plain floats (the HIP vector classes cannot be
+// copied out of another address space).
+__device__ __forceinline__ cptr<float> uniform_ptr(const float2 *p) { return (cptr<float>)p; }
+__device__ __forceinline__ cptr<float> uniform_ptr(const float4 *p) { return (cptr<float>)p; }
+__device__ __forceinline__ cptr<uint32_t> uniform_ptr(const uint32_t *p) { return (cptr<uint32_t>)p; }
+
+__device__ __forceinline__ float2 ld2(cptr<float> p, int i) { return make_float2(p[2 * i], p[2 * i + 1]); }
 
 __device__ __forceinline__ int gray_code(int m) { return m ^ (m >> 1); }
 __device__ __forceinline__ int gray_decode(int g) { return g ^ (g >> 1) ^ (g >> 2); }
@@ -35,276 +59,238 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks)
 }
 
 // ============================================================================
-// a4: choice of the k-th closest constellation point at one depth.
-// Distances are taken per axis, e(m) = (u - (2m - L + 1) a)^2 with
-// a = R_ll * Delta, so |b - R_ll c|^2 = e_I(mI) + e_Q(mQ).  Order: distance,
-// then constellation index (gray(mI) << HB | gray(mQ)).
+// a4: choice of the k-th closest constellation point at one depth, in lattice
+// units.  Level index m in 0..L-1 <-> level value 2m - (L-1).
 // ============================================================================
 template <int L>
-__device__ __forceinline__ float axis_err(float u, float a, int m)
+__device__ __forceinline__ float level_of(float m)
 {
-    const float dlt = fmaf(-(float)(2 * m - (L - 1)), a, u);
-    return dlt * dlt;
+    return fmaf(m, 2.f, -(float)(L - 1));
 }
 
+// closest level: round the level coordinate, clamp to the constellation
 template <int L>
-__device__ __forceinline__ int axis_nearest(float u, float a, float inv2a, float &e)
+__device__ __forceinline__ float nearest_level(float z, float &m)
 {
-    float pos = fmaf(u, inv2a, 0.5f * (float)(L - 1));
-    pos = fminf(fmaxf(pos, 0.f), (float)(L - 1));
-    const int m0 = (int)floorf(pos);
-    const int m1 = min(m0 + 1, L - 1);
-    const float e0 = axis_err<L>(u, a, m0), e1 = axis_err<L>(u, a, m1);
-    const bool t1 = (e1 < e0) || (e1 == e0 && gray_code(m1) < gray_code(m0));
-    e = t1 ? e1 : e0;
-    return t1 ? m1 : m0;
+    m = __builtin_amdgcn_fmed3f(rintf(fmaf(z, 0.5f, 0.5f * (float)(L - 1))), 0.f, (float)(L - 1));
+    return level_of<L>(m);
 }
 
-// second closest level on one axis: the better neighbour of the closest
+// second closest level of one axis: the neighbour of the closest level m0
+// on the side of z, or the other neighbour at the edge of the constellation
 template <int L>
-__device__ __forceinline__ int axis_second(float u, float a, int m0, float &e)
+__device__ __forceinline__ void axis_second(float z, float m0, float lv0, float &m1, float &e1)
 {
-    const int lo = m0 - 1, hi = m0 + 1;
-    const float elo = lo >= 0 ? axis_err<L>(u, a, lo) : INFINITY;
-    const float ehi = hi < L ? axis_err<L>(u, a, hi) : INFINITY;
-    bool take_hi;
-    if (lo < 0)
-        take_hi = true;
-    else if (hi >= L)
-        take_hi = false;
-    else
-        take_hi = (ehi < elo) || (ehi == elo && gray_code(hi) < gray_code(lo));
-    e = take_hi ? ehi : elo;
-    return take_hi ? hi : lo;
+    const float s = (z >= lv0) ? 1.f : -1.f;
+    const float a = m0 + s;
+    m1 = (a >= 0.f && a <= (float)(L - 1)) ? a : m0 - s;
+    const float d1 = z - level_of<L>(m1);
+    e1 = d1 * d1;
 }
 
+// Exact k-th closest point for any k (used for k > 4): merge of L sorted
+// rows, one per in-phase level, over the quadrature levels sorted by
+// distance; every row's next candidate is kept, the smallest is taken k
+// times.  Equal costs resolve to the lower in-phase level.
 template <int L>
-__device__ __noinline__ void kth_general(float2 b, float a, float inv2a, int k, int &mI, int &mQ,
-                                         float &dist)
+__device__ __forceinline__ void kth_lattice(float zI, float zQ, int k, float &mI, float &mQ, float &eIo,
+                                            float &eQo)
 {
-    constexpr int HB = Axis<L>::HB;
-    // quadrature axis sorted by (distance, gray label): two-pointer zig-zag
-    float eq0;
-    const int mq0 = axis_nearest<L>(b.y, a, inv2a, eq0);
-    int ordQ[L], gQ[L];
+    // quadrature levels sorted by distance: two-pointer walk from the closest
+    float mq0;
+    nearest_level<L>(zQ, mq0);
+    int ordQ[L];
     float eQ[L];
-    ordQ[0] = mq0;
-    eQ[0] = eq0;
-    int lo = mq0 - 1, hi = mq0 + 1;
+    {
+        const int q0 = (int)mq0;
+        ordQ[0] = q0;
+        const float dd = zQ - level_of<L>((float)q0);
+        eQ[0] = dd * dd;
+        int lo = q0 - 1, hi = q0 + 1;
 #pragma unroll
-    for (int t = 1; t < L; ++t) {
-        const float elo = lo >= 0 ? axis_err<L>(b.y, a, lo) : INFINITY;
-        const float ehi = hi < L ? axis_err<L>(b.y, a, hi) : INFINITY;
-        bool take_hi;
-        if (lo < 0)
-            take_hi = true;
-        else if (hi >= L)
-            take_hi = false;
-        else
-            take_hi = (ehi < elo) || (ehi == elo && gray_code(hi) < gray_code(lo));
-        ordQ[t] = take_hi ? hi : lo;
-        eQ[t] = take_hi ? ehi : elo;
-        hi += take_hi ? 1 : 0;
-        lo -= take_hi ? 0 : 1;
+        for (int t = 1; t < L; ++t) {
+            const float dl = zQ - level_of<L>((float)lo), dh = zQ - level_of<L>((float)hi);
+            const float elo = lo >= 0 ? dl * dl : INFINITY;
+            const float ehi = hi < L ? dh * dh : INFINITY;
+            const bool take_hi = ehi < elo || lo < 0;
+            ordQ[t] = take_hi ? hi : lo;
+            eQ[t] = take_hi ? ehi : elo;
+            hi += take_hi ? 1 : 0;
+            lo -= take_hi ? 0 : 1;
+        }
     }
-#pragma unroll
-    for (int t = 0; t < L; ++t)
-        gQ[t] = gray_code(ordQ[t]);
-    // one sorted row per in-phase level; L-way merge of the rows
-    float eI[L], cand[L];
-    int gI[L], ptr[L], cidx[L];
+    int ptr[L];
+    float cand[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-        eI[i] = axis_err<L>(b.x, a, i);
-        gI[i] = gray_code(i) << HB;
+        const float dd = zI - level_of<L>((float)i);
         ptr[i] = 0;
-        cand[i] = eI[i] + eQ[0];
-        cidx[i] = gI[i] | gQ[0];
+        cand[i] = dd * dd + eQ[0];
     }
     int bi = 0;
-    float bc = cand[0];
     for (int step = 0;; ++step) {
         bi = 0;
-        bc = cand[0];
-        int bx = cidx[0];
+        float bc = cand[0];
 #pragma unroll
         for (int i = 1; i < L; ++i) {
-            const bool lt = cand[i] < bc || (cand[i] == bc && cidx[i] < bx);
+            const bool lt = cand[i] < bc;
             bi = lt ? i : bi;
             bc = lt ? cand[i] : bc;
-            bx = lt ? cidx[i] : bx;
         }
         if (step >= k - 1 || step >= L * L - 1)
             break;
-        int p = 0, gi = 0;
-        float ei = 0.f;
 #pragma unroll
         for (int i = 0; i < L; ++i)
             if (i == bi) {
-                p = ptr[i];
-                ei = eI[i];
-                gi = gI[i];
-            }
-        ++p;
-        float eq = INFINITY;
-        int gq = 0;
+                const int p = ptr[i] + 1;
+                float eq = INFINITY;
 #pragma unroll
-        for (int t = 0; t < L; ++t)
-            if (t == p) {
-                eq = eQ[t];
-                gq = gQ[t];
-            }
-        const float nc = ei + eq;
-#pragma unroll
-        for (int i = 0; i < L; ++i)
-            if (i == bi) {
+                for (int t = 1; t < L; ++t)
+                    eq = (t == p) ? eQ[t] : eq;
+                const float dd = zI - level_of<L>((float)i);
                 ptr[i] = p;
-                cand[i] = nc;
-                cidx[i] = gi | gq;
+                cand[i] = dd * dd + eq;
             }
     }
     int pp = 0;
 #pragma unroll
     for (int i = 0; i < L; ++i)
-        if (i == bi)
-            pp = ptr[i];
-    int mq = 0;
+        pp = (i == bi) ? ptr[i] : pp;
+    int mq = ordQ[0];
+    float eq = eQ[0];
 #pragma unroll
-    for (int t = 0; t < L; ++t)
-        if (t == pp)
-            mq = ordQ[t];
-    mI = bi;
-    mQ = mq;
-    dist = bc;
-}
-
-template <int L>
-__device__ __forceinline__ void select_point(float2 b, float a, float inv2a, int k, int &mI, int &mQ,
-                                             float &dist)
-{
-    constexpr int HB = Axis<L>::HB;
-    if (a == 0.f) {  // R_ll = 0: every point is equally far; index order decides
-        const int idx = min(max(k - 1, 0), L * L - 1);
-        mI = gray_decode(idx >> HB);
-        mQ = gray_decode(idx & (L - 1));
-        dist = b.x * b.x + b.y * b.y;
-        return;
+    for (int t = 1; t < L; ++t) {
+        mq = (t == pp) ? ordQ[t] : mq;
+        eq = (t == pp) ? eQ[t] : eq;
     }
-    float eI0, eQ0;
-    const int mI0 = axis_nearest<L>(b.x, a, inv2a, eI0);
-    const int mQ0 = axis_nearest<L>(b.y, a, inv2a, eQ0);
-    if (k <= 1) {
-        mI = mI0;
-        mQ = mQ0;
-        dist = eI0 + eQ0;
-    } else if (k == 2) {
-        float eI1, eQ1;
-        const int mI1 = axis_second<L>(b.x, a, mI0, eI1);
-        const int mQ1 = axis_second<L>(b.y, a, mQ0, eQ1);
-        const float cA = eI0 + eQ1;  // (closest I, second Q)
-        const float cB = eI1 + eQ0;  // (second I, closest Q)
-        const int iA = (gray_code(mI0) << HB) | gray_code(mQ1);
-        const int iB = (gray_code(mI1) << HB) | gray_code(mQ0);
-        const bool tb = (cB < cA) || (cB == cA && iB < iA);
-        mI = tb ? mI1 : mI0;
-        mQ = tb ? mQ0 : mQ1;
-        dist = tb ? cB : cA;
-    } else {
-        kth_general<L>(b, a, inv2a, k, mI, mQ, dist);
-    }
+    const float dI = zI - level_of<L>((float)bi);
+    mI = (float)bi;
+    mQ = (float)mq;
+    eIo = dI * dI;
+    eQo = eq;
 }
 
 // ============================================================================
 // a4 + a5: path search.
 // ============================================================================
 struct PathArgs {
-    const float2 *yt;       // (T, S, N)
-    const float4 *diag;     // (S, N)
-    const float2 *roff;     // (S, N, N)
-    const uint32_t *roffq;  // (S, N, N) half2 / bf16x2 of R * Delta, or null
-    const int32_t *permd;   // (S, N)
-    const uint8_t *P;       // (S, K, NP)
-    int32_t *out;           // (T, S, N)
-    float *llr;             // (T, S, N, bits) or null
+    const float2 *yt;      // (T, S, N) rotated received vectors, lattice units
+    const float4 *diag;    // (S, N) (a^2 or 1, R_ll == 0, 1/a or 1, R_ll)
+    const float2 *rlat;    // (S, N, N) R in lattice units
+    const uint32_t *rq;    // (S, N, N) half2 / bf16x2 of rlat, or null
+    const int32_t *permd;  // (S, N)
+    const uint8_t *P;      // (S, K, NP)
+    int32_t *out;          // (T, S, N)
+    float *llr;            // (T, S, N, bits) or null
+    float *part;           // per path group best (metric, path, decisions) or null
     int S, T, N, K, NP;
-    float delta, sigma2, clip;
+    float sigma2, clip;
 };
 
 enum { PREC_FP32 = 0, PREC_FP16 = 1, PREC_BF16 = 2 };
 
-// One SIC descent driven by the position vector in pw.  Residuals b[e] for
-// the depths e not yet decided are updated right after each decision
-// (b_e -= R_{l_e, l_d} s_d).  Returns the accumulated metric; the chosen
-// constellation indices are packed four per word into dec.
-template <int NMAX, int L, int PREC>
-__device__ __forceinline__ float descend(const float2 *__restrict__ yv, const float4 *__restrict__ dg,
-                                        const float2 *__restrict__ roff,
-                                        const uint32_t *__restrict__ roffq, int N,
-                                        const uint32_t *pw, uint32_t *dec, float delta)
+// Decisions are packed as level codes c = mI + L mQ (< 64), four per float:
+// digit d & 3 of decf[d >> 2] in base 64, exact in a float mantissa.
+__device__ __forceinline__ constexpr float code_weight(int d)
 {
-    constexpr int HB = Axis<L>::HB;
-    float2 b[NMAX];
+    return (d & 3) == 0 ? 1.f : (d & 3) == 1 ? 64.f : (d & 3) == 2 ? 4096.f : 262144.f;
+}
+
+// One SIC descent driven by the position vector in pw.  After each decision
+// the residuals of the depths below are updated, b_e -= R'[d][e] s_d.
+template <int N, int L, int PREC>
+__device__ __forceinline__ float descend(cptr<float> yv, cptr<float> dg, cptr<float> rl,
+                                        cptr<uint32_t> rq, const uint32_t *pw, float *decf)
+{
+    float2 b[N];
 #pragma unroll
-    for (int d = 0; d < NMAX; ++d)
-        if (d < N)
-            b[d] = yv[d];
+    for (int d = 0; d < N; ++d)
+        b[d] = ld2(yv, d);
     float metric = 0.f;
 #pragma unroll
-    for (int d = 0; d < NMAX; ++d) {
-        if (d < N) {
+    for (int d = 0; d < N; ++d) {
         const int k = (pw[d >> 2] >> ((d & 3) * 8)) & 0xff;
-        const float4 g = dg[d];
-        int mI, mQ;
-        float dist;
-        select_point<L>(b[d], g.y, g.z, k, mI, mQ, dist);
-        metric += dist;
-        const int idx = (gray_code(mI) << HB) | gray_code(mQ);
-        dec[d >> 2] |= (uint32_t)idx << ((d & 3) * 8);
-        const int lI = 2 * mI - (L - 1), lQ = 2 * mQ - (L - 1);
-        if constexpr (PREC == PREC_FP32) {
-            const float sI = (float)lI * delta, sQ = (float)lQ * delta;
-#pragma unroll
-            for (int e = d + 1; e < NMAX; ++e) {
-                if (e < N) {
-                    const float2 r = roff[d * N + e];
-                    b[e].x = fmaf(-r.x, sI, b[e].x);
-                    b[e].x = fmaf(r.y, sQ, b[e].x);
-                    b[e].y = fmaf(-r.x, sQ, b[e].y);
-                    b[e].y = fmaf(-r.y, sI, b[e].y);
+        const float gw = dg[4 * d], gzero = dg[4 * d + 1];
+        const float zI = b[d].x, zQ = b[d].y;
+        float mI, mQ, eI, eQ;
+        if (gzero != 0.f) {
+            // R_ll = 0: every point is equally far; the k-th in index order
+            const int idx = min(max(k - 1, 0), L * L - 1);
+            mI = (float)gray_decode(idx >> Axis<L>::HB);
+            mQ = (float)gray_decode(idx & (L - 1));
+            eI = zI * zI;
+            eQ = zQ * zQ;
+        } else {
+            const float lI = nearest_level<L>(zI, mI), lQ = nearest_level<L>(zQ, mQ);
+            const float dI = zI - lI, dQ = zQ - lQ;
+            eI = dI * dI;
+            eQ = dQ * dQ;
+            if (k == 2) {
+                // rank 2 is (second I, closest Q) or (closest I, second Q):
+                // every other point is farther than one of the two
+                float mI1, eI1, mQ1, eQ1;
+                axis_second<L>(zI, mI, lI, mI1, eI1);
+                axis_second<L>(zQ, mQ, lQ, mQ1, eQ1);
+                if (eI1 + eQ <= eI + eQ1) {
+                    mI = mI1;
+                    eI = eI1;
+                } else {
+                    mQ = mQ1;
+                    eQ = eQ1;
                 }
+            } else if (k > 2) {
+                kth_lattice<L>(zI, zQ, k, mI, mQ, eI, eQ);
+            }
+        }
+        metric = fmaf(gw, eI + eQ, metric);
+        decf[d >> 2] = fmaf(fmaf(mQ, (float)L, mI), code_weight(d), decf[d >> 2]);
+        const float sI = level_of<L>(mI), sQ = level_of<L>(mQ);
+        if constexpr (PREC == PREC_FP32) {
+#pragma unroll
+            for (int e = d + 1; e < N; ++e) {
+                const float2 r = ld2(rl, d * N + e);
+                b[e].x = fmaf(-r.x, sI, b[e].x);
+                b[e].x = fmaf(r.y, sQ, b[e].x);
+                b[e].y = fmaf(-r.x, sQ, b[e].y);
+                b[e].y = fmaf(-r.y, sI, b[e].y);
             }
         } else if constexpr (PREC == PREC_FP16) {
-            half2_t sa, sb;  // (-sI, sQ) and (-sQ, -sI) as exact small integers
-            sa.x = (_Float16)(float)(-lI);
-            sa.y = (_Float16)(float)(lQ);
-            sb.x = (_Float16)(float)(-lQ);
-            sb.y = (_Float16)(float)(-lI);
+            half2_t sa, sb;  // (-sI, sQ) and (-sQ, -sI): small odd integers, exact
+            sa.x = (_Float16)(-sI);
+            sa.y = (_Float16)sQ;
+            sb.x = (_Float16)(-sQ);
+            sb.y = (_Float16)(-sI);
 #pragma unroll
-            for (int e = d + 1; e < NMAX; ++e) {
-                if (e < N) {
-                    const half2_t r = __builtin_bit_cast(half2_t, roffq[d * N + e]);
-                    b[e].x = __builtin_amdgcn_fdot2(r, sa, b[e].x, false);
-                    b[e].y = __builtin_amdgcn_fdot2(r, sb, b[e].y, false);
-                }
+            for (int e = d + 1; e < N; ++e) {
+                const half2_t r = __builtin_bit_cast(half2_t, rq[d * N + e]);
+                b[e].x = __builtin_amdgcn_fdot2(r, sa, b[e].x, false);
+                b[e].y = __builtin_amdgcn_fdot2(r, sb, b[e].y, false);
             }
         } else {
             bf162_t sa, sb;
-            sa.x = (__bf16)(float)(-lI);
-            sa.y = (__bf16)(float)(lQ);
-            sb.x = (__bf16)(float)(-lQ);
-            sb.y = (__bf16)(float)(-lI);
+            sa.x = (__bf16)(-sI);
+            sa.y = (__bf16)sQ;
+            sb.x = (__bf16)(-sQ);
+            sb.y = (__bf16)(-sI);
 #pragma unroll
-            for (int e = d + 1; e < NMAX; ++e) {
-                if (e < N) {
-                    const bf162_t r = __builtin_bit_cast(bf162_t, roffq[d * N + e]);
-                    b[e].x = __builtin_amdgcn_fdot2_f32_bf16(r, sa, b[e].x, false);
-                    b[e].y = __builtin_amdgcn_fdot2_f32_bf16(r, sb, b[e].y, false);
-                }
+            for (int e = d + 1; e < N; ++e) {
+                const bf162_t r = __builtin_bit_cast(bf162_t, rq[d * N + e]);
+                b[e].x = __builtin_amdgcn_fdot2_f32_bf16(r, sa, b[e].x, false);
+                b[e].y = __builtin_amdgcn_fdot2_f32_bf16(r, sb, b[e].y, false);
             }
-        }
         }
     }
     return (metric == metric) ? metric : INFINITY;
+}
+
+// constellation index chosen at depth d of a packed decision record
+template <int L>
+__device__ __forceinline__ int32_t decision_index(const float *decf, int d)
+{
+    const uint32_t word = (uint32_t)decf[d >> 2];
+    const int code = (int)((word >> (6 * (d & 3))) & 63u);
+    const int mI = code & (L - 1), mQ = (code >> Axis<L>::HB) & (L - 1);
+    return (gray_code(mI) << Axis<L>::HB) | gray_code(mQ);
 }
 
 __device__ __forceinline__ bool better(float m, int r, float bm, int br)
@@ -312,43 +298,9 @@ __device__ __forceinline__ bool better(float m, int r, float bm, int br)
     return m < bm || (m == bm && r < br);
 }
 
-template <int NMAX, int L, int PREC>
-__global__ __launch_bounds__(256) void path_search_kernel(PathArgs a)
+// Minimum (metric, path) over the workgroup; returns the winning path index.
+__device__ __forceinline__ int block_argmin(float bm, int br, float *sm, int *sr)
 {
-    constexpr int NW = NMAX / 4;
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int s = lb / a.T, t = lb - s * a.T;
-    const int N = a.N;
-    const float2 *yv = a.yt + ((size_t)t * a.S + s) * N;
-    const float4 *dg = a.diag + (size_t)s * N;
-    const float2 *roff = a.roff + (size_t)s * N * N;
-    const uint32_t *roffq = a.roffq ? a.roffq + (size_t)s * N * N : nullptr;
-    const int nw = a.NP >> 2;
-    const uint32_t *Pw = (const uint32_t *)(a.P + (size_t)s * a.K * a.NP);
-
-    float bm = INFINITY;
-    int br = INT_MAX;
-    uint32_t bdec[NW];
-#pragma unroll
-    for (int w = 0; w < NW; ++w)
-        bdec[w] = 0;
-    for (int r = threadIdx.x; r < a.K; r += blockDim.x) {
-        uint32_t pw[NW], dec[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            pw[w] = (w < nw) ? Pw[(size_t)r * nw + w] : 0x01010101u;
-            dec[w] = 0;
-        }
-        const float m = descend<NMAX, L, PREC>(yv, dg, roff, roffq, N, pw, dec, a.delta);
-        if (better(m, r, bm, br)) {
-            bm = m;
-            br = r;
-#pragma unroll
-            for (int w = 0; w < NW; ++w)
-                bdec[w] = dec[w];
-        }
-    }
-    // a5: minimum metric over the workgroup (equal metrics: lowest path)
     float wm = bm;
     int wr = br;
 #pragma unroll
@@ -360,8 +312,6 @@ __global__ __launch_bounds__(256) void path_search_kernel(PathArgs a)
             wr = orr;
         }
     }
-    __shared__ float sm[4];
-    __shared__ int sr[4];
     const int wid = threadIdx.x >> 6;
     const int nwv = (blockDim.x + 63) >> 6;
     if ((threadIdx.x & 63) == 0) {
@@ -376,63 +326,140 @@ __global__ __launch_bounds__(256) void path_search_kernel(PathArgs a)
             gm = sm[w];
             gr = sr[w];
         }
-    if (br == gr) {
-        int32_t *o = a.out + ((size_t)t * a.S + s) * N;
-        const int32_t *pm = a.permd + (size_t)s * N;
+    return gr;
+}
+
+// One lane runs one path: lane tid of path group g runs path g * blockDim +
+// tid of one received vector.  With one group the winner writes its symbols
+// in user order; with several, each group leaves its best (metric, path,
+// decisions) for path_group_reduce_kernel.
+template <int N, int L, int PREC>
+__device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cptr<float> rl,
+                                              cptr<uint32_t> rq, const uint8_t *Pbase, int K, int NP,
+                                              int group, const int32_t *pm, int32_t *o,
+                                              float *part, float *sm, int *sr)
+{
+    constexpr int NW = (N + 3) / 4;
+    const uint32_t *Pw = (const uint32_t *)Pbase;
+    const int nw = NP >> 2;
+    const int r = group * (int)blockDim.x + (int)threadIdx.x;
+    float bm = INFINITY;
+    int br = INT_MAX;
+    float decf[NW];
 #pragma unroll
-        for (int d = 0; d < NMAX; ++d) {
-            if (d < N) {
-                const int u = pm[d];
-                if ((unsigned)u < (unsigned)N)  // permd is a permutation for finite inputs
-                    o[u] = (int32_t)((bdec[d >> 2] >> ((d & 3) * 8)) & 0xffu);
-            }
+    for (int w = 0; w < NW; ++w)
+        decf[w] = 0.f;
+    if (r < K) {
+        uint32_t pw[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+            pw[w] = Pw[(size_t)r * nw + w];
+        bm = descend<N, L, PREC>(yv, dg, rl, rq, pw, decf);
+        br = r;
+    }
+    const int gr = block_argmin(bm, br, sm, sr);
+    if (br != gr)
+        return;
+    if (part == nullptr) {
+#pragma unroll
+        for (int d = 0; d < N; ++d) {
+            const int u = pm[d];
+            if ((unsigned)u < (unsigned)N)  // permd is a permutation for finite inputs
+                o[u] = decision_index<L>(decf, d);
         }
+    } else {
+        part[0] = bm;
+        part[1] = __int_as_float(br);
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+            part[2 + w] = decf[w];
+    }
+}
+
+// grid: (S * T) x path groups; partials: (S * T, groups, 2 + (N + 3) / 4)
+template <int N, int L, int PREC>
+__global__ __launch_bounds__(256) void path_search_kernel(PathArgs a)
+{
+    __shared__ float sm[4];
+    __shared__ int sr[4];
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = lb / a.T, t = lb - s * a.T;
+    const size_t sN = (size_t)s * N;
+    const size_t v = (size_t)t * a.S + s;
+    cptr<uint32_t> rq = a.rq ? uniform_ptr(a.rq + sN * N) : nullptr;
+    float *part = a.part ? a.part + (v * gridDim.y + blockIdx.y) * (2 + (N + 3) / 4) : nullptr;
+    search_vector<N, L, PREC>(uniform_ptr(a.yt + v * N), uniform_ptr(a.diag + sN), uniform_ptr(a.rlat + sN * N),
+                              rq, a.P + (size_t)s * a.K * a.NP, a.K, a.NP, blockIdx.y, a.permd + sN,
+                              a.out + v * N, part, sm, sr);
+}
+
+// Best of the path groups of every received vector (equal metrics: lowest
+// path), written in user order.  One lane per vector.
+template <int L>
+__global__ __launch_bounds__(256) void path_group_reduce_kernel(PathArgs a, int groups)
+{
+    const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= (size_t)a.S * a.T)
+        return;
+    const int N = a.N;
+    const int stride = 2 + (N + 3) / 4;
+    const float *p = a.part + v * groups * stride;
+    int best = 0;
+    for (int g = 1; g < groups; ++g)
+        if (better(p[g * stride], __float_as_int(p[g * stride + 1]), p[best * stride],
+                   __float_as_int(p[best * stride + 1])))
+            best = g;
+    const float *dec = p + best * stride + 2;
+    const int s = (int)(v % a.S);
+    const int32_t *pm = a.permd + (size_t)s * N;
+    for (int d = 0; d < N; ++d) {
+        const int u = pm[d];
+        if ((unsigned)u < (unsigned)N)
+            a.out[v * N + u] = decision_index<L>(dec, d);
     }
 }
 
 // ============================================================================
-// a4 + a5 with max-log soft output: every path's metric and symbols go to
-// LDS; for each (user, bit) the smallest metric with the bit at 0 and at 1
-// is found by one lane scanning the K paths.
+// a4 + a5 with max-log soft output: every path's metric and decisions go to
+// LDS; for each (user, bit) one lane scans the K paths for the smallest
+// metric with the bit at 0 and at 1.
 // ============================================================================
-template <int NMAX, int L>
-__global__ __launch_bounds__(256) void path_search_soft_kernel(PathArgs a)
+template <int N, int L>
+__device__ __forceinline__ void soft_vector(const PathArgs &a, int s, int t, unsigned char *smem)
 {
-    constexpr int NW = NMAX / 4;
+    constexpr int NW = (N + 3) / 4;
     constexpr int HB = Axis<L>::HB;
     constexpr int BITS = 2 * HB;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int s = lb / a.T, t = lb - s * a.T;
-    const int N = a.N, K = a.K;
-    const float2 *yv = a.yt + ((size_t)t * a.S + s) * N;
-    const float4 *dg = a.diag + (size_t)s * N;
-    const float2 *roff = a.roff + (size_t)s * N * N;
+    const int K = a.K;
+    const size_t sN = (size_t)s * N;
+    cptr<float> yv = uniform_ptr(a.yt + ((size_t)t * a.S + s) * N);
+    cptr<float> dg = uniform_ptr(a.diag + sN);
+    cptr<float> rl = uniform_ptr(a.rlat + sN * N);
     const int nw = a.NP >> 2;
     const uint32_t *Pw = (const uint32_t *)(a.P + (size_t)s * K * a.NP);
-    float *mets = (float *)smem;                   // K
-    uint32_t *decs = (uint32_t *)(mets + K);       // K * NW
-
+    float *mets = (float *)smem;          // K
+    float *decs = mets + K;               // K * NW
     for (int r = threadIdx.x; r < K; r += blockDim.x) {
-        uint32_t pw[NW], dec[NW];
+        uint32_t pw[NW];
+        float decf[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-            pw[w] = (w < nw) ? Pw[(size_t)r * nw + w] : 0x01010101u;
-            dec[w] = 0;
+            pw[w] = Pw[(size_t)r * nw + w];
+            decf[w] = 0.f;
         }
-        mets[r] = descend<NMAX, L, PREC_FP32>(yv, dg, roff, nullptr, N, pw, dec, a.delta);
+        mets[r] = descend<N, L, PREC_FP32>(yv, dg, rl, nullptr, pw, decf);
 #pragma unroll
         for (int w = 0; w < NW; ++w)
-            decs[(size_t)r * NW + w] = dec[w];
+            decs[(size_t)r * NW + w] = decf[w];
     }
     __syncthreads();
-    const int32_t *pm = a.permd + (size_t)s * N;
+    const int32_t *pm = a.permd + sN;
     const size_t vbase = ((size_t)t * a.S + s) * N;
     for (int q = threadIdx.x; q < N * BITS; q += blockDim.x) {
         const int d = q / BITS, bit = q - d * BITS;
         float m0 = INFINITY, m1 = INFINITY;
         for (int r = 0; r < K; ++r) {
-            const int idx = (decs[(size_t)r * NW + (d >> 2)] >> ((d & 3) * 8)) & 0xff;
+            const int idx = decision_index<L>(decs + (size_t)r * NW, d);
             const float m = mets[r];
             if ((idx >> (BITS - 1 - bit)) & 1)
                 m1 = fminf(m1, m);
@@ -461,28 +488,52 @@ __global__ __launch_bounds__(256) void path_search_soft_kernel(PathArgs a)
         for (int d = 0; d < N; ++d) {
             const int u = pm[d];
             if ((unsigned)u < (unsigned)N)
-                a.out[vbase + u] = (int32_t)((decs[(size_t)br * NW + (d >> 2)] >> ((d & 3) * 8)) & 0xffu);
+                a.out[vbase + u] = decision_index<L>(decs + (size_t)br * NW, d);
         }
     }
+    __syncthreads();
+}
+
+// Instantiate f<N> for the user counts of one bucket (NMAX-7 .. NMAX) and
+// call the one matching the runtime N (uniform across the workgroup).
+#define MPNL_BUCKET_SWITCH(NMAX, N, CALL)                                                          \
+    switch ((NMAX) - (N)) {                                                                        \
+    case 0: { constexpr int NN = (NMAX); CALL; } break;                                            \
+    case 1: { constexpr int NN = (NMAX) - 1; CALL; } break;                                        \
+    case 2: { constexpr int NN = (NMAX) - 2; CALL; } break;                                        \
+    case 3: { constexpr int NN = (NMAX) - 3; CALL; } break;                                        \
+    case 4: { constexpr int NN = (NMAX) - 4; CALL; } break;                                        \
+    case 5: { constexpr int NN = (NMAX) - 5; CALL; } break;                                        \
+    case 6: { constexpr int NN = (NMAX) - 6; CALL; } break;                                        \
+    case 7: { constexpr int NN = (NMAX) - 7; CALL; } break;                                        \
+    default: break;                                                                                \
+    }
+
+template <int NMAX, int L>
+__global__ __launch_bounds__(256) void path_search_soft_kernel(PathArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = lb / a.T, t = lb - s * a.T;
+    MPNL_BUCKET_SWITCH(NMAX, a.N, (soft_vector<NN, L>(a, s, t, smem)))
 }
 
 // ============================================================================
 // Batched path search: one persistent launch for many jobs (cells) of one
-// (NMAX bucket, modulation).  Workgroups take (job, subcarrier, symbol) items
-// from a device counter until the queue is empty; every item is processed
-// exactly as path_search_kernel would, so results equal the per-job launch.
+// (user-count bucket, modulation).  Workgroups take (job, subcarrier,
+// symbol) items from a device counter until the queue is empty; each item is
+// processed exactly as path_search_kernel processes it, so the result of a
+// job does not depend on the other jobs in the batch.
 // ============================================================================
 struct BatchArgs {
     const JobDev *jobs;
     int n_jobs, total_items;
     unsigned *counter;
-    float delta;
 };
 
 template <int NMAX, int L>
 __global__ __launch_bounds__(256) void path_search_batch_kernel(BatchArgs a)
 {
-    constexpr int NW = NMAX / 4;
     __shared__ int item_s;
     __shared__ float sm[4];
     __shared__ int sr[4];
@@ -494,90 +545,26 @@ __global__ __launch_bounds__(256) void path_search_batch_kernel(BatchArgs a)
         __syncthreads();
         if (item >= a.total_items)
             break;
-        int jb = 0;  // job owning the item (jobs sorted by item_begin)
-        {
-            int lo = 0, hi = a.n_jobs - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (a.jobs[mid].item_begin <= item)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            jb = lo;
+        int lo = 0, hi = a.n_jobs - 1;  // job owning the item (jobs sorted by item_begin)
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.jobs[mid].item_begin <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
         }
-        const JobDev j = a.jobs[jb];
+        const JobDev j = a.jobs[lo];
         const int li = item - j.item_begin;
         const int s = li / j.T, t = li - s * j.T;
-        const int N = j.N;
-        const float2 *yv = j.yt + ((size_t)t * j.S + s) * N;
-        const float4 *dg = j.diag + (size_t)s * N;
-        const float2 *roff = j.roff + (size_t)s * N * N;
-        const int nw = j.NP >> 2;
-        const uint32_t *Pw = (const uint32_t *)(j.P + (size_t)s * j.K * j.NP);
-        float bm = INFINITY;
-        int br = INT_MAX;
-        uint32_t bdec[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w)
-            bdec[w] = 0;
-        for (int r = threadIdx.x; r < j.K; r += blockDim.x) {
-            uint32_t pw[NW], dec[NW];
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                pw[w] = (w < nw) ? Pw[(size_t)r * nw + w] : 0x01010101u;
-                dec[w] = 0;
-            }
-            const float m = descend<NMAX, L, PREC_FP32>(yv, dg, roff, nullptr, N, pw, dec, a.delta);
-            if (better(m, r, bm, br)) {
-                bm = m;
-                br = r;
-#pragma unroll
-                for (int w = 0; w < NW; ++w)
-                    bdec[w] = dec[w];
-            }
-        }
-        float wm = bm;
-        int wr = br;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const float om = __shfl_xor(wm, off);
-            const int orr = __shfl_xor(wr, off);
-            if (better(om, orr, wm, wr)) {
-                wm = om;
-                wr = orr;
-            }
-        }
-        const int wid = threadIdx.x >> 6;
-        const int nwv = (blockDim.x + 63) >> 6;
-        if ((threadIdx.x & 63) == 0) {
-            sm[wid] = wm;
-            sr[wid] = wr;
-        }
-        __syncthreads();
-        float gm = sm[0];
-        int gr = sr[0];
-        for (int w = 1; w < nwv; ++w)
-            if (better(sm[w], sr[w], gm, gr)) {
-                gm = sm[w];
-                gr = sr[w];
-            }
-        if (br == gr) {
-            int32_t *o = j.out + ((size_t)t * j.S + s) * N;
-            const int32_t *pm = j.permd + (size_t)s * N;
-#pragma unroll
-            for (int d = 0; d < NMAX; ++d) {
-                if (d < N) {
-                    const int u = pm[d];
-                    if ((unsigned)u < (unsigned)N)
-                        o[u] = (int32_t)((bdec[d >> 2] >> ((d & 3) * 8)) & 0xffu);
-                }
-            }
-        }
+        const size_t sN = (size_t)s * j.N;
+        MPNL_BUCKET_SWITCH(NMAX, j.N,
+                           (search_vector<NN, L, PREC_FP32>(
+                               uniform_ptr(j.yt + ((size_t)t * j.S + s) * NN), uniform_ptr(j.diag + sN),
+                               uniform_ptr(j.rlat + sN * NN), nullptr, j.P + (size_t)s * j.K * j.NP, j.K,
+                               j.NP, 0, j.permd + sN, j.out + ((size_t)t * j.S + s) * NN, nullptr, sm, sr)))
         __syncthreads();
     }
 }
-
 
 inline float delta_of(int bits)
 {

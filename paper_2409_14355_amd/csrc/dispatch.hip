@@ -1,12 +1,40 @@
-// Dispatch of the path-search launches to the user-count buckets.
+// Dispatch of the path-search launches to the per-user-count kernels.
 #include "device_common.h"
 
 namespace mpnl {
 
-hipError_t path_launch_nmax8(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_nmax16(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_nmax24(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_nmax32(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n1(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n2(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n3(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n4(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n5(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n6(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n7(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n8(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n9(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n10(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n11(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n12(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n13(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n14(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n15(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n16(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n17(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n18(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n19(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n20(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n21(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n22(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n23(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n24(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n25(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n26(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n27(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n28(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n29(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n30(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n31(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_launch_n32(const dev::PathArgs &, int, int, hipStream_t);
 hipError_t soft_launch_nmax8(const dev::PathArgs &, int, hipStream_t);
 hipError_t soft_launch_nmax16(const dev::PathArgs &, int, hipStream_t);
 hipError_t soft_launch_nmax24(const dev::PathArgs &, int, hipStream_t);
@@ -18,23 +46,59 @@ hipError_t batch_launch_nmax32(const dev::BatchArgs &, int, int, int, hipStream_
 
 namespace {
 using namespace dev;
+
+typedef hipError_t (*PathLaunch)(const PathArgs &, int, int, hipStream_t);
+const PathLaunch kPathLaunch[32] = {
+    path_launch_n1,
+    path_launch_n2,
+    path_launch_n3,
+    path_launch_n4,
+    path_launch_n5,
+    path_launch_n6,
+    path_launch_n7,
+    path_launch_n8,
+    path_launch_n9,
+    path_launch_n10,
+    path_launch_n11,
+    path_launch_n12,
+    path_launch_n13,
+    path_launch_n14,
+    path_launch_n15,
+    path_launch_n16,
+    path_launch_n17,
+    path_launch_n18,
+    path_launch_n19,
+    path_launch_n20,
+    path_launch_n21,
+    path_launch_n22,
+    path_launch_n23,
+    path_launch_n24,
+    path_launch_n25,
+    path_launch_n26,
+    path_launch_n27,
+    path_launch_n28,
+    path_launch_n29,
+    path_launch_n30,
+    path_launch_n31,
+    path_launch_n32};
+
 PathArgs path_args(const SlotDev &sd, const float2 *yt, int T, int32_t *out)
 {
     PathArgs a;
     a.yt = yt;
     a.diag = sd.diag;
-    a.roff = sd.roff;
-    a.roffq = nullptr;
+    a.rlat = sd.rlat;
+    a.rq = nullptr;
     a.permd = sd.permd;
     a.P = sd.P;
     a.out = out;
     a.llr = nullptr;
+    a.part = nullptr;
     a.S = sd.S;
     a.T = T;
     a.N = sd.N;
     a.K = sd.K;
     a.NP = sd.NP;
-    a.delta = delta_of(sd.bits);
     a.sigma2 = 1.f;
     a.clip = 0.f;
     return a;
@@ -42,17 +106,44 @@ PathArgs path_args(const SlotDev &sd, const float2 *yt, int T, int32_t *out)
 
 }  // namespace
 
-hipError_t launch_path_search_q(const SlotDev &sd, const float2 *yt, int T, int32_t *out,
-                                int precision, const uint32_t *roffq, hipStream_t st)
+int nmax_bucket(int N)
 {
+    return N <= 8 ? 8 : N <= 16 ? 16 : N <= 24 ? 24 : 32;
+}
+
+size_t path_partial_bytes(const SlotDev &sd, int T)
+{
+    const int groups = (sd.K + 255) / 256;
+    if (groups <= 1)
+        return 0;
+    return (size_t)sd.S * T * groups * (2 + (sd.N + 3) / 4) * sizeof(float);
+}
+
+hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_t *out,
+                              int precision, float *part, hipStream_t st)
+{
+    if (sd.N < 1 || sd.N > 32)
+        return hipErrorInvalidValue;
     PathArgs a = path_args(sd, yt, T, out);
-    a.roffq = roffq;
-    switch (nmax_bucket(sd.N)) {
-    case 8: return path_launch_nmax8(a, sd.bits, precision, st);
-    case 16: return path_launch_nmax16(a, sd.bits, precision, st);
-    case 24: return path_launch_nmax24(a, sd.bits, precision, st);
-    default: return path_launch_nmax32(a, sd.bits, precision, st);
+    a.rq = precision == PREC_FP16 ? sd.rlat_h : precision == PREC_BF16 ? sd.rlat_b : nullptr;
+    const int groups = (sd.K + 255) / 256;
+    if (groups > 1) {
+        if (part == nullptr)
+            return hipErrorInvalidValue;
+        a.part = part;
     }
+    hipError_t e = kPathLaunch[sd.N - 1](a, sd.bits, precision, st);
+    if (e != hipSuccess || groups <= 1)
+        return e;
+    const int vecs = sd.S * T;
+    const dim3 grid((vecs + 255) / 256), block(256);
+    if (sd.bits == 2)
+        hipLaunchKernelGGL(path_group_reduce_kernel<2>, grid, block, 0, st, a, groups);
+    else if (sd.bits == 4)
+        hipLaunchKernelGGL(path_group_reduce_kernel<4>, grid, block, 0, st, a, groups);
+    else
+        hipLaunchKernelGGL(path_group_reduce_kernel<8>, grid, block, 0, st, a, groups);
+    return hipGetLastError();
 }
 
 hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, float sigma2,
@@ -79,7 +170,6 @@ hipError_t launch_path_search_batch(const JobDev *jobs_dev, int n_jobs, int tota
     a.n_jobs = n_jobs;
     a.total_items = total_items;
     a.counter = counter;
-    a.delta = delta_of(bits);
     switch (nmax_bkt) {
     case 8: return batch_launch_nmax8(a, bits, threads, grid, st);
     case 16: return batch_launch_nmax16(a, bits, threads, grid, st);

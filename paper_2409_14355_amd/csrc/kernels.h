@@ -14,7 +14,10 @@ struct SlotDev {
     int NP;                // position-vector row stride in bytes (N rounded up to 4)
     float2 *Qd;            // (S, M, N)  column d = Q[:, N-1-d]
     float2 *roff;          // (S, N, N)  [d][d'] = R[N-1-d'][N-1-d] for d' > d
-    float4 *diag;          // (S, N)     (R_ll, R_ll*Delta, 1/(2 R_ll Delta) or 0, 0)
+    float2 *rlat;          // (S, N, N)  the same entries in lattice units, times Delta / a_{d'}
+    uint32_t *rlat_h;      // (S, N, N)  rlat as half2 (MPNL_PREC_FP16)
+    uint32_t *rlat_b;      // (S, N, N)  rlat as bf16x2 (MPNL_PREC_BF16)
+    float4 *diag;          // (S, N)     (a^2 or 1, R_ll == 0, 1/a or 1, R_ll), a = R_ll Delta
     double *wd;            // (S, N)     R_ll^2 from the float64 pivot norm
     int32_t *permd;        // (S, N)     original user detected at depth d
     uint8_t *P;            // (S, K, NP) ranks 1..|Q| per depth, padded with 1
@@ -23,8 +26,8 @@ struct SlotDev {
 
 // Work item of the batched path search: one job (cell) of an uneven batch.
 struct JobDev {
-    const float2 *yt;      // (T, S, N) rotated received vectors, depth order
-    const float2 *roff;
+    const float2 *yt;      // (T, S, N) rotated received vectors, depth order, lattice units
+    const float2 *rlat;
     const float4 *diag;
     const int32_t *permd;
     const uint8_t *P;
@@ -34,14 +37,15 @@ struct JobDev {
 };
 
 // Kernel launchers (enqueue only; return hipError_t of the launch).
-// a1; also writes R * Delta as half2 / bf16x2 for the reduced-precision path search.
-hipError_t launch_sqrd_q(const float2 *H, const SlotDev &sd, uint32_t *roff_h, uint32_t *roff_b,
-                         hipStream_t st);
+// a1; writes R both as is (roff) and in lattice units (rlat, rlat_h, rlat_b).
+hipError_t launch_sqrd(const float2 *H, const SlotDev &sd, hipStream_t st);
 hipError_t launch_posvec(const SlotDev &sd, hipStream_t st);
 hipError_t launch_rotate(const SlotDev &sd, const float2 *y, int T, float2 *yt, hipStream_t st);
-// roffq: the half2 / bf16x2 copy of R matching `precision` (null for float32).
-hipError_t launch_path_search_q(const SlotDev &sd, const float2 *yt, int T, int32_t *out,
-                                int precision, const uint32_t *roffq, hipStream_t st);
+// K > 256 paths run as ceil(K / 256) workgroups per vector whose best
+// paths meet in `part` (path_partial_bytes(); null when K <= 256).
+size_t path_partial_bytes(const SlotDev &sd, int T);
+hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_t *out,
+                              int precision, float *part, hipStream_t st);
 hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, float sigma2,
                                    float clip, float *llr, int32_t *out, hipStream_t st);
 // Batched path search over many jobs sharing (NMAX bucket, bits); one persistent launch.

@@ -1,3 +1,3 @@
-// Path-search kernels for up to 16 users.
-#define MPNL_NMAX 16
-#include "path_inst.inc"
+// Path-search kernels for 16 users.
+#define MPNL_N 16
+#include "path_exact.inc"

@@ -1,3 +1,3 @@
-// Path-search kernels for up to 24 users.
-#define MPNL_NMAX 24
-#include "path_inst.inc"
+// Path-search kernels for 24 users.
+#define MPNL_N 24
+#include "path_exact.inc"

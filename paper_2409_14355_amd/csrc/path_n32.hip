@@ -1,3 +1,3 @@
-// Path-search kernels for up to 32 users.
-#define MPNL_NMAX 32
-#include "path_inst.inc"
+// Path-search kernels for 32 users.
+#define MPNL_N 32
+#include "path_exact.inc"

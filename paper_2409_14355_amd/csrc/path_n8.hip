@@ -1,3 +1,3 @@
-// Path-search kernels for up to 8 users.
-#define MPNL_NMAX 8
-#include "path_inst.inc"
+// Path-search kernels for 8 users.
+#define MPNL_N 8
+#include "path_exact.inc"

@@ -21,8 +21,6 @@ struct SqrdArgs {
     int S, M, N;
     float delta;
     SlotDev sd;
-    uint32_t *roff_h;  // (S, N, N) half2 of R * Delta  (MPNL_PREC_FP16)
-    uint32_t *roff_b;  // (S, N, N) bf16x2 of R * Delta (MPNL_PREC_BF16)
 };
 
 __device__ __forceinline__ uint32_t pack_half2(float x, float y)
@@ -144,12 +142,19 @@ __global__ __launch_bounds__(64) void sqrd_kernel(SqrdArgs a)
     }
 
     // ---- outputs of R, in depth order ----
+    // a = R_ll * Delta of every row, shared so that entries can be put in the
+    // lattice units of the row they update
+    __shared__ float INVA[2][kMaxN];
     const int d = N - 1 - pos;
+    const float rll = (float)sqrt(wnorm);
+    const float aa = rll * a.delta;
+    const float inva = aa > 0.f ? 1.f / aa : 1.f;
+    if (active)
+        INVA[half][pos] = inva;
+    __syncthreads();
     if (active) {
         const size_t sN = (size_t)s * N;
-        const float rll = (float)sqrt(wnorm);
-        const float aa = rll * a.delta;
-        a.sd.diag[sN + d] = make_float4(rll, aa, aa > 0.f ? 1.f / (2.f * aa) : 0.f, 0.f);
+        a.sd.diag[sN + d] = make_float4(aa > 0.f ? aa * aa : 1.f, aa > 0.f ? 0.f : 1.f, inva, rll);
         a.sd.wd[sN + d] = wnorm;
         a.sd.permd[sN + d] = c;
 #pragma unroll
@@ -157,9 +162,12 @@ __global__ __launch_bounds__(64) void sqrd_kernel(SqrdArgs a)
             if (m < pos) {
                 const int d2 = N - 1 - m;
                 const size_t o = (sN + d) * N + d2;
+                const float sc = a.delta * INVA[half][m];
+                const float lx = col[m].x * sc, ly = col[m].y * sc;
                 a.sd.roff[o] = col[m];
-                a.roff_h[o] = pack_half2(col[m].x * a.delta, col[m].y * a.delta);
-                a.roff_b[o] = bf16_bits(col[m].x * a.delta) | (bf16_bits(col[m].y * a.delta) << 16);
+                a.sd.rlat[o] = make_float2(lx, ly);
+                a.sd.rlat_h[o] = pack_half2(lx, ly);
+                a.sd.rlat_b[o] = bf16_bits(lx) | (bf16_bits(ly) << 16);
             }
         }
     }
@@ -400,7 +408,8 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
 }
 
 // ============================================================================
-// a3: yt = Q^H y on MFMA.  Real form of the complex product:
+// a3: yt = Q^H y on MFMA, each row then put in lattice units (times 1/a_l).
+// Real form of the complex product:
 //   [Re yt_d]   sum_m [ qr  qi ] [yr_m]
 //   [Im yt_d] =       [-qi  qr ] [yi_m]
 // A (2N x 2M) times B (2M x T) with v_mfma_f32_16x16x4_f32: lane l supplies
@@ -409,6 +418,7 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 struct RotArgs {
+    const float4 *diag;  // (S, N) .z = 1/a of the row
     const float2 *Qd;  // (S, M, N)
     const float2 *y;   // (T, S, M)
     float2 *yt;        // (T, S, N)
@@ -451,7 +461,7 @@ __global__ __launch_bounds__(64) void rotate_kernel(RotArgs a)
                 const int orow = rt * 16 + 4 * kq + v;
                 const int od = orow >> 1, opart = orow & 1;
                 if (od < N && tt < T)
-                    yt[(((size_t)tt * S + s) * N + od) * 2 + opart] = acc[v];
+                    yt[(((size_t)tt * S + s) * N + od) * 2 + opart] = acc[v] * a.diag[(size_t)s * N + od].z;
             }
         }
     }
@@ -459,7 +469,7 @@ __global__ __launch_bounds__(64) void rotate_kernel(RotArgs a)
 
 
 template <int MMAX>
-hipError_t sqrd_launch_t(const float2 *H, const SlotDev &sd, uint32_t *rh, uint32_t *rb, hipStream_t st)
+hipError_t sqrd_launch_t(const float2 *H, const SlotDev &sd, hipStream_t st)
 {
     SqrdArgs a;
     a.H = H;
@@ -468,8 +478,6 @@ hipError_t sqrd_launch_t(const float2 *H, const SlotDev &sd, uint32_t *rh, uint3
     a.N = sd.N;
     a.delta = delta_of(sd.bits);
     a.sd = sd;
-    a.roff_h = rh;
-    a.roff_b = rb;
     const int grid = (sd.S + 1) / 2;
     hipLaunchKernelGGL(sqrd_kernel<MMAX>, dim3(grid), dim3(64), 0, st, a);
     return hipGetLastError();
@@ -480,10 +488,6 @@ hipError_t sqrd_launch_t(const float2 *H, const SlotDev &sd, uint32_t *rh, uint3
 using namespace dev;
 
 
-int nmax_bucket(int N)
-{
-    return N <= 8 ? 8 : N <= 16 ? 16 : N <= 24 ? 24 : 32;
-}
 
 bool posvec_rec_fits_lds(int N, int K)
 {
@@ -500,19 +504,18 @@ size_t posvec_lds_bytes(int N, int K, bool rec_in_lds)
     return b;
 }
 
-hipError_t launch_sqrd_q(const float2 *H, const SlotDev &sd, uint32_t *roff_h, uint32_t *roff_b,
-                         hipStream_t st)
+hipError_t launch_sqrd(const float2 *H, const SlotDev &sd, hipStream_t st)
 {
     const int mm = ((sd.M + 3) / 4) * 4;
     switch (mm) {
-    case 4: return sqrd_launch_t<4>(H, sd, roff_h, roff_b, st);
-    case 8: return sqrd_launch_t<8>(H, sd, roff_h, roff_b, st);
-    case 12: return sqrd_launch_t<12>(H, sd, roff_h, roff_b, st);
-    case 16: return sqrd_launch_t<16>(H, sd, roff_h, roff_b, st);
-    case 20: return sqrd_launch_t<20>(H, sd, roff_h, roff_b, st);
-    case 24: return sqrd_launch_t<24>(H, sd, roff_h, roff_b, st);
-    case 28: return sqrd_launch_t<28>(H, sd, roff_h, roff_b, st);
-    case 32: return sqrd_launch_t<32>(H, sd, roff_h, roff_b, st);
+    case 4: return sqrd_launch_t<4>(H, sd, st);
+    case 8: return sqrd_launch_t<8>(H, sd, st);
+    case 12: return sqrd_launch_t<12>(H, sd, st);
+    case 16: return sqrd_launch_t<16>(H, sd, st);
+    case 20: return sqrd_launch_t<20>(H, sd, st);
+    case 24: return sqrd_launch_t<24>(H, sd, st);
+    case 28: return sqrd_launch_t<28>(H, sd, st);
+    case 32: return sqrd_launch_t<32>(H, sd, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -545,6 +548,7 @@ hipError_t launch_posvec(const SlotDev &sd, hipStream_t st)
 hipError_t launch_rotate(const SlotDev &sd, const float2 *y, int T, float2 *yt, hipStream_t st)
 {
     RotArgs a;
+    a.diag = sd.diag;
     a.Qd = sd.Qd;
     a.y = y;
     a.yt = yt;

@@ -32,8 +32,6 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct mpnl_slot {
     mpnl::SlotDev sd{};
-    uint32_t *roff_h = nullptr;
-    uint32_t *roff_b = nullptr;
     int block = -1;
     hipStream_t stream = nullptr;  // stream of the last work that used the slot
 };
@@ -238,7 +236,7 @@ int validate_shape(int S, int M, int N, int mod, int n_paths)
 
 // Offsets of the slot arrays inside one pool block.
 struct SlotLayout {
-    size_t Qd, roff, roff_h, roff_b, diag, wd, permd, P, rec, total;
+    size_t Qd, roff, rlat, rlat_h, rlat_b, diag, wd, permd, P, rec, total;
 };
 
 SlotLayout slot_layout(int S, int M, int N, int K, int NP, bool rec_global)
@@ -252,8 +250,9 @@ SlotLayout slot_layout(int S, int M, int N, int K, int NP, bool rec_global)
     const size_t sNN = (size_t)S * N * N;
     put(L.Qd, (size_t)S * M * N * sizeof(float2));
     put(L.roff, sNN * sizeof(float2));
-    put(L.roff_h, sNN * sizeof(uint32_t));
-    put(L.roff_b, sNN * sizeof(uint32_t));
+    put(L.rlat, sNN * sizeof(float2));
+    put(L.rlat_h, sNN * sizeof(uint32_t));
+    put(L.rlat_b, sNN * sizeof(uint32_t));
     put(L.diag, (size_t)S * N * sizeof(float4));
     put(L.wd, (size_t)S * N * sizeof(double));
     put(L.permd, (size_t)S * N * sizeof(int32_t));
@@ -289,19 +288,20 @@ int prepare_impl(mpnl_ctx *ctx, const void *H, int S, int M, int N, int mod, int
     sd.NP = NP;
     sd.Qd = (float2 *)(base + L.Qd);
     sd.roff = (float2 *)(base + L.roff);
+    sd.rlat = (float2 *)(base + L.rlat);
+    sd.rlat_h = (uint32_t *)(base + L.rlat_h);
+    sd.rlat_b = (uint32_t *)(base + L.rlat_b);
     sd.diag = (float4 *)(base + L.diag);
     sd.wd = (double *)(base + L.wd);
     sd.permd = (int32_t *)(base + L.permd);
     sd.P = (uint8_t *)(base + L.P);
     sd.rec = rec_global ? (uint32_t *)(base + L.rec) : nullptr;
-    slot->roff_h = (uint32_t *)(base + L.roff_h);
-    slot->roff_b = (uint32_t *)(base + L.roff_b);
     slot->block = blk;
     slot->stream = st;
     hipError_t e;
     {
         StageTimer tm(ctx, MPNL_STAGE_SQRD, st);
-        e = mpnl::launch_sqrd_q((const float2 *)H, sd, slot->roff_h, slot->roff_b, st);
+        e = mpnl::launch_sqrd((const float2 *)H, sd, st);
     }
     if (e == hipSuccess) {
         StageTimer tm(ctx, MPNL_STAGE_POSVEC, st);
@@ -335,11 +335,19 @@ int detect_impl(mpnl_ctx *ctx, mpnl_slot *slot, const void *y, int T, int32_t *o
     const mpnl::SlotDev &sd = slot->sd;
     if ((long long)sd.S * T > INT_MAX / 2)
         return MPNL_E_UNSUPPORTED;
+    const size_t yt_bytes = (size_t)T * sd.S * sd.N * sizeof(float2);
+    const size_t part_bytes = soft ? 0 : mpnl::path_partial_bytes(sd, T);
     int blk = -1;
-    int rc = pool_alloc(ctx, (size_t)T * sd.S * sd.N * sizeof(float2), st, &blk);
+    int rc = pool_alloc(ctx, align_up(yt_bytes) + part_bytes, st, &blk);
     if (rc != MPNL_OK)
         return rc;
-    float2 *yt = (float2 *)ctx->blocks[blk].ptr;
+    char *base = (char *)ctx->blocks[blk].ptr;
+    float2 *yt = (float2 *)base;
+    float *part = part_bytes ? (float *)(base + align_up(yt_bytes)) : nullptr;
+    if (part_bytes && align_up(yt_bytes) + part_bytes > ctx->blocks[blk].size) {
+        pool_release(ctx, blk, st);
+        return MPNL_E_NOMEM;
+    }
     hipError_t e;
     {
         StageTimer tm(ctx, MPNL_STAGE_ROTATE, st);
@@ -347,14 +355,10 @@ int detect_impl(mpnl_ctx *ctx, mpnl_slot *slot, const void *y, int T, int32_t *o
     }
     if (e == hipSuccess) {
         StageTimer tm(ctx, MPNL_STAGE_PATHS, st);
-        if (soft) {
+        if (soft)
             e = mpnl::launch_path_search_soft(sd, yt, T, sigma2, clip, llr, out, st);
-        } else {
-            const uint32_t *q = ctx->precision == MPNL_PREC_FP16   ? slot->roff_h
-                                : ctx->precision == MPNL_PREC_BF16 ? slot->roff_b
-                                                                   : nullptr;
-            e = mpnl::launch_path_search_q(sd, yt, T, out, ctx->precision, q, st);
-        }
+        else
+            e = mpnl::launch_path_search(sd, yt, T, out, ctx->precision, part, st);
     }
     pool_release(ctx, blk, st);
     slot->stream = st;
@@ -615,15 +619,21 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
         return hip_fail(ctx, hipErrorInvalidDevice);
     hipStream_t st = (hipStream_t)stream;
 
-    // a1-a3 per job
+    // a1-a3 per job; a job with more than 256 paths also runs its own a4+a5
     std::vector<mpnl_slot *> slots(n_jobs, nullptr);
     std::vector<int> ytb(n_jobs, -1);
+    std::vector<char> batched(n_jobs, 0);
     int rc = MPNL_OK;
     for (int i = 0; i < n_jobs && rc == MPNL_OK; ++i) {
         const mpnl_job &j = jobs[i];
         rc = prepare_impl(ctx, j.H, j.S, j.M, j.N, j.mod, j.n_paths, st, &slots[i]);
         if (rc != MPNL_OK)
             break;
+        if (slots[i]->sd.K > 256) {
+            rc = detect_impl(ctx, slots[i], j.y, j.T, j.out, st, false, 0.f, 0.f, nullptr);
+            continue;
+        }
+        batched[i] = 1;
         rc = pool_alloc(ctx, (size_t)j.T * j.S * j.N * sizeof(float2), st, &ytb[i]);
         if (rc != MPNL_OK)
             break;
@@ -637,19 +647,24 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
             rc = hip_fail(ctx, e);
     }
 
-    // a4+a5: one persistent launch per (user-count bucket, modulation)
+    // a4+a5: one persistent launch per (user-count bucket, modulation,
+    // workgroup size = paths rounded up to a wavefront)
     if (rc == MPNL_OK) {
         struct Group {
-            int bucket, bits;
+            int bucket, bits, threads;
             std::vector<int> idx;
         };
         std::vector<Group> groups;
         for (int i = 0; i < n_jobs; ++i) {
+            if (!batched[i])
+                continue;
             const int bk = mpnl::nmax_bucket(jobs[i].N), bits = jobs[i].mod;
-            auto it = std::find_if(groups.begin(), groups.end(),
-                                   [&](const Group &q) { return q.bucket == bk && q.bits == bits; });
+            const int thr = (slots[i]->sd.K + 63) / 64 * 64;
+            auto it = std::find_if(groups.begin(), groups.end(), [&](const Group &q) {
+                return q.bucket == bk && q.bits == bits && q.threads == thr;
+            });
             if (it == groups.end()) {
-                groups.push_back({bk, bits, {}});
+                groups.push_back({bk, bits, thr, {}});
                 it = groups.end() - 1;
             }
             it->idx.push_back(i);
@@ -680,21 +695,21 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
                 rc = hip_fail(ctx, e);
         }
         int tblk = -1;
-        if (rc == MPNL_OK)
+        if (rc == MPNL_OK && !groups.empty())
             rc = pool_alloc(ctx, table_bytes, st, &tblk);
-        if (rc == MPNL_OK) {
+        if (rc == MPNL_OK && !groups.empty()) {
             char *host = (char *)ctx->pinned;
             char *dev = (char *)ctx->blocks[tblk].ptr;
             std::vector<int> items(groups.size()), threads(groups.size());
             for (size_t q = 0; q < groups.size(); ++q) {
                 mpnl::JobDev *jd = (mpnl::JobDev *)(host + goff[q]);
-                int acc = 0, thr = 64;
+                int acc = 0;
                 for (size_t u = 0; u < groups[q].idx.size(); ++u) {
                     const int i = groups[q].idx[u];
                     const mpnl::SlotDev &sd = slots[i]->sd;
                     mpnl::JobDev &J = jd[u];
                     J.yt = (const float2 *)ctx->blocks[ytb[i]].ptr;
-                    J.roff = sd.roff;
+                    J.rlat = sd.rlat;
                     J.diag = sd.diag;
                     J.permd = sd.permd;
                     J.P = sd.P;
@@ -706,12 +721,11 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
                     J.NP = sd.NP;
                     J.item_begin = acc;
                     acc += sd.S * jobs[i].T;
-                    thr = std::max(thr, sd.K >= 256 ? 256 : (sd.K + 63) / 64 * 64);
                 }
                 unsigned *cnt = (unsigned *)(host + goff[q] + groups[q].idx.size() * sizeof(mpnl::JobDev));
                 cnt[0] = 0;
                 items[q] = acc;
-                threads[q] = thr;
+                threads[q] = groups[q].threads;
             }
             hipError_t e = hipMemcpyAsync(dev, host, table_bytes, hipMemcpyHostToDevice, st);
             if (e == hipSuccess)

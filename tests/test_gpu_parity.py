@@ -301,10 +301,14 @@ def test_reduced_precision_close_to_fp64(ctx, mp, prec):
 
 
 # ---------------------------------------------------------- soft output ---
-def test_soft_output_matches_oracle(ctx):
-    _say("soft")
-    S, T, M, N, bits, K = 12, 3, 6, 4, 4, 64
-    sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=10, seed=(214,))
+@pytest.mark.parametrize("snr,K,bits", [(10, 64, 4), (0, 200, 4), (2, 300, 6), (-3, 256, 2)])
+def test_soft_output_matches_oracle(ctx, snr, K, bits):
+    """Max-log LLRs use every path's metric, so they check the k-th-best
+    choice of all paths, including received points far outside the
+    constellation (low SNR) and more paths than one workgroup."""
+    _say("soft", snr, K, bits)
+    S, T, M, N = 12, 3, 6, 4
+    sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=snr, seed=(214, snr + 100, K))
     slot = ctx.slot_prepare(_dev(sl.H), bits, K)
     out = torch.empty((T, S, N), dtype=torch.int32, device="cuda:0")
     llr = slot.detect_soft(_dev(sl.y), sl.sigma2, 50.0, out=out)
