@@ -38,8 +38,17 @@ def sources() -> list[str]:
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str, hipcc: str, verbose: bool) -> str:
+def _headers_mtime() -> float:
+    names = [f for f in os.listdir(CSRC) if f.endswith((".h", ".inc"))]
+    names = [os.path.join(CSRC, f) for f in names] + [os.path.join(INCLUDE, "mpnl.h")]
+    return max(os.path.getmtime(f) for f in names)
+
+
+def _compile(src: str, hipcc: str, verbose: bool, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
+    if incremental and os.path.exists(obj) and \
+            os.path.getmtime(obj) > max(os.path.getmtime(src), _headers_mtime()):
+        return obj
     cmd = [hipcc, *CFLAGS, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -49,12 +58,14 @@ def _compile(src: str, hipcc: str, verbose: bool) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every translation unit (only the out-of-date ones when
+    `incremental`) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, hipcc, verbose), sources()))
+        objs = list(ex.map(lambda s: _compile(s, hipcc, verbose, incremental), sources()))
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -65,4 +76,4 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

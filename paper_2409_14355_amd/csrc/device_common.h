@@ -58,6 +58,14 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks)
     return xcd * q + min(xcd, rem) + local;
 }
 
+// a2 arguments (position-vector set kernels)
+struct PosArgs {
+    const double *w;  // (S, N)
+    int S, N, nq, K, NP;
+    uint8_t *P;       // (S, K, NP)
+    uint32_t *rec_g;  // (S, N, K) when the back pointers do not fit in LDS
+};
+
 // ============================================================================
 // a4: choice of the k-th closest constellation point at one depth, in lattice
 // units.  Level index m in 0..L-1 <-> level value 2m - (L-1).

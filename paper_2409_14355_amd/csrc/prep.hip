@@ -228,12 +228,6 @@ __global__ __launch_bounds__(64) void sqrd_kernel(SqrdArgs a)
 // lexicographic order of the extended prefixes.  Back pointers
 // (parent, k) per depth rebuild the vectors at the end.
 // ============================================================================
-struct PosArgs {
-    const double *w;  // (S, N)
-    int S, N, nq, K, NP;
-    uint8_t *P;       // (S, K, NP)
-    uint32_t *rec_g;  // (S, N, K) when the back pointers do not fit in LDS
-};
 
 __device__ __forceinline__ bool key_less(double sa, int la, int ka, double sb, int lb, int kb)
 {
@@ -520,6 +514,8 @@ hipError_t launch_sqrd(const float2 *H, const SlotDev &sd, hipStream_t st)
     }
 }
 
+hipError_t launch_posvec_reg(const dev::PosArgs &a, hipStream_t st);
+
 hipError_t launch_posvec(const SlotDev &sd, hipStream_t st)
 {
     PosArgs a;
@@ -531,6 +527,8 @@ hipError_t launch_posvec(const SlotDev &sd, hipStream_t st)
     a.NP = sd.NP;
     a.P = sd.P;
     a.rec_g = sd.rec;
+    if (sd.K <= 256)
+        return launch_posvec_reg(a, st);
     const bool in_lds = posvec_rec_fits_lds(sd.N, sd.K);
     const size_t lds = posvec_lds_bytes(sd.N, sd.K, in_lds);
     if (in_lds) {

@@ -104,6 +104,30 @@ def test_position_set_stage(ctx, S, M, N, bits, K):
             assert set(map(tuple, P[s].tolist())) == set(map(tuple, Pr.tolist())) or bmargin < 1e-12, s
 
 
+@pytest.mark.parametrize("M,N,bits,K", [(4, 4, 2, 200), (6, 6, 4, 256), (5, 5, 2, 64), (8, 8, 6, 1000)])
+def test_position_set_exact_ties(ctx, M, N, bits, K):
+    """Identity channels give exactly equal weights (all 1.0) and zeroed
+    columns give zero weights: the set and its order are then decided by the
+    lexicographic rule alone."""
+    _say("posvec ties", M, N, bits, K)
+    H = np.zeros((3, M, N), np.complex64)
+    for s in range(3):
+        H[s, :N, :N] = np.eye(N)
+    H[1, :, 1] = 0
+    H[2, :, 0] = 0
+    H[2, :, N - 1] = 0
+    slot = ctx.slot_prepare(_dev(H), bits, K)
+    ex = slot.export()
+    torch.cuda.synchronize()
+    w = ex["w"].cpu().numpy()
+    P = ex["P"].cpu().numpy()
+    slot.release()
+    assert np.all(np.isin(w, [0.0, 1.0]))
+    for s in range(3):
+        Pr, _, _ = oracle.position_set(w[s], 1 << bits, K)
+        assert np.array_equal(P[s], Pr), s
+
+
 # ------------------------------------------------------------- end to end ---
 CASES = [
     # name, S, T, M, N, bits, snr, K, channel
