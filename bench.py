@@ -67,6 +67,8 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-subcarriers", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 256 MiB device copy (a counter calibration kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (independent "
@@ -91,6 +93,12 @@ def main() -> int:
     ctx.set_precision(PRECISIONS[args.precision])
     Kc = min(K, (1 << bits) ** N)
 
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         ctx.detect(H, y, bits, K, out)
     torch.cuda.synchronize()

@@ -63,6 +63,7 @@ struct PosArgs {
     const double *w;  // (S, N)
     int S, N, nq, K, NP;
     uint8_t *P;       // (S, K, NP)
+    uint16_t *order;  // (S, K) path run by each lane, or null (identity)
     uint32_t *rec_g;  // (S, N, K) when the back pointers do not fit in LDS
 };
 
@@ -94,6 +95,72 @@ __device__ __forceinline__ void axis_second(float z, float m0, float lv0, float 
     m1 = (a >= 0.f && a <= (float)(L - 1)) ? a : m0 - s;
     const float d1 = z - level_of<L>(m1);
     e1 = d1 * d1;
+}
+
+// levels of rank 1..3 of one axis (rank 0 = m0, at level lv0): the zig-zag
+// from m0 that starts on the side of z, levels beyond the constellation
+// skipped.  With |z - lv0| <= 1 the zig-zag is sorted by distance; when z
+// lies beyond the outermost level only one side exists and the order is
+// monotone.  Missing ranks (L = 2) get infinite distances.
+template <int L>
+__device__ __forceinline__ void axis_ranks3(float z, float m0, float lv0, float (&m)[3], float (&e)[3])
+{
+    const float s = (z >= lv0) ? 1.f : -1.f;
+    const float cp = s > 0.f ? (float)(L - 1) - m0 : m0;  // levels on side +s
+    const float cm = (float)(L - 1) - cp;                  // levels on side -s
+    const float q = fminf(cp, cm);
+    const float far = cp > cm ? s : -s;
+#pragma unroll
+    for (int t = 1; t <= 3; ++t) {
+        const float ti = (t & 1) ? m0 + s * (float)((t + 1) / 2) : m0 - s * (float)(t / 2);
+        const float to = m0 + far * ((float)t - q);
+        const float mt = ((float)t <= 2.f * q) ? ti : to;
+        const float dd = z - level_of<L>(mt);
+        m[t - 1] = mt;
+        e[t - 1] = (t <= L - 1) ? dd * dd : INFINITY;
+    }
+}
+
+// Exact 3rd or 4th closest point from the per-axis orders: ranks 2..4 of
+// the sum of two sorted lists lie on the frontier {(1,0), (0,1)}, then
+// {(2,0), (0,1)} or {(1,0), (0,2)}, then one of (3,0), (2,0), (1,1), (0,2),
+// (0,3) depending on the earlier ranks.  Equal costs: the in-phase step first.
+template <int L>
+__device__ __forceinline__ void kth_small(float zI, float zQ, int k, float &mI, float lI, float &eI,
+                                          float &mQ, float lQ, float &eQ)
+{
+    float mi[3], ei[3], mq[3], eq[3];
+    axis_ranks3<L>(zI, mI, lI, mi, ei);
+    axis_ranks3<L>(zQ, mQ, lQ, mq, eq);
+    const float e0I = eI, e0Q = eQ;
+    const float c10 = ei[0] + e0Q, c01 = e0I + eq[0];
+    const float c20 = ei[1] + e0Q, c02 = e0I + eq[1];
+    const bool firstI = c10 <= c01;
+    const bool third20 = firstI && c20 <= c01;   // ranks 2, 3 = (1,0), (2,0)
+    const bool third02 = !firstI && c02 < c10;   // ranks 2, 3 = (0,1), (0,2)
+    int ci, cj;
+    if (k == 3) {
+        ci = firstI ? (third20 ? 2 : 0) : (third02 ? 0 : 1);
+        cj = firstI ? (third20 ? 0 : 1) : (third02 ? 2 : 0);
+    } else if (third20) {
+        const bool a = ei[2] + e0Q <= c01;       // (3,0) or (0,1)
+        ci = a ? 3 : 0;
+        cj = a ? 0 : 1;
+    } else if (third02) {
+        const bool a = c10 <= e0I + eq[2];       // (1,0) or (0,3)
+        ci = a ? 1 : 0;
+        cj = a ? 0 : 3;
+    } else {
+        const float c11 = ei[0] + eq[0];         // (2,0), (1,1) or (0,2)
+        const bool a = c20 <= c11 && c20 <= c02;
+        const bool b = !a && c11 <= c02;
+        ci = a ? 2 : b ? 1 : 0;
+        cj = a ? 0 : b ? 1 : 2;
+    }
+    mI = ci == 0 ? mI : ci == 1 ? mi[0] : ci == 2 ? mi[1] : mi[2];
+    eI = ci == 0 ? e0I : ci == 1 ? ei[0] : ci == 2 ? ei[1] : ei[2];
+    mQ = cj == 0 ? mQ : cj == 1 ? mq[0] : cj == 2 ? mq[1] : mq[2];
+    eQ = cj == 0 ? e0Q : cj == 1 ? eq[0] : cj == 2 ? eq[1] : eq[2];
 }
 
 // Exact k-th closest point for any k (used for k > 4): merge of L sorted
@@ -188,6 +255,7 @@ struct PathArgs {
     const uint32_t *rq;    // (S, N, N) half2 / bf16x2 of rlat, or null
     const int32_t *permd;  // (S, N)
     const uint8_t *P;      // (S, K, NP)
+    const uint16_t *order; // (S, K) path run by each lane, or null (identity)
     int32_t *out;          // (T, S, N)
     float *llr;            // (T, S, N, bits) or null
     float *part;           // per path group best (metric, path, decisions) or null
@@ -246,7 +314,9 @@ __device__ __forceinline__ float descend(cptr<float> yv, cptr<float> dg, cptr<fl
                     mQ = mQ1;
                     eQ = eQ1;
                 }
-            } else if (k > 2) {
+            } else if (k == 3 || k == 4) {
+                kth_small<L>(zI, zQ, k, mI, lI, eI, mQ, lQ, eQ);
+            } else if (k > 4) {
                 kth_lattice<L>(zI, zQ, k, mI, mQ, eI, eQ);
             }
         }
@@ -343,21 +413,23 @@ __device__ __forceinline__ int block_argmin(float bm, int br, float *sm, int *sr
 // decisions) for path_group_reduce_kernel.
 template <int N, int L, int PREC>
 __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cptr<float> rl,
-                                              cptr<uint32_t> rq, const uint8_t *Pbase, int K, int NP,
-                                              int group, const int32_t *pm, int32_t *o,
-                                              float *part, float *sm, int *sr)
+                                              cptr<uint32_t> rq, const uint8_t *Pbase,
+                                              const uint16_t *order, int K, int NP, int group,
+                                              const int32_t *pm, int32_t *o, float *part, float *sm,
+                                              int *sr)
 {
     constexpr int NW = (N + 3) / 4;
     const uint32_t *Pw = (const uint32_t *)Pbase;
     const int nw = NP >> 2;
-    const int r = group * (int)blockDim.x + (int)threadIdx.x;
+    const int li = group * (int)blockDim.x + (int)threadIdx.x;
     float bm = INFINITY;
     int br = INT_MAX;
     float decf[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w)
         decf[w] = 0.f;
-    if (r < K) {
+    if (li < K) {
+        const int r = order ? (int)order[li] : li;
         uint32_t pw[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w)
@@ -397,8 +469,8 @@ __global__ __launch_bounds__(256) void path_search_kernel(PathArgs a)
     cptr<uint32_t> rq = a.rq ? uniform_ptr(a.rq + sN * N) : nullptr;
     float *part = a.part ? a.part + (v * gridDim.y + blockIdx.y) * (2 + (N + 3) / 4) : nullptr;
     search_vector<N, L, PREC>(uniform_ptr(a.yt + v * N), uniform_ptr(a.diag + sN), uniform_ptr(a.rlat + sN * N),
-                              rq, a.P + (size_t)s * a.K * a.NP, a.K, a.NP, blockIdx.y, a.permd + sN,
-                              a.out + v * N, part, sm, sr);
+                              rq, a.P + (size_t)s * a.K * a.NP, a.order ? a.order + (size_t)s * a.K : nullptr,
+                              a.K, a.NP, blockIdx.y, a.permd + sN, a.out + v * N, part, sm, sr);
 }
 
 // Best of the path groups of every received vector (equal metrics: lowest
@@ -568,8 +640,9 @@ __global__ __launch_bounds__(256) void path_search_batch_kernel(BatchArgs a)
         MPNL_BUCKET_SWITCH(NMAX, j.N,
                            (search_vector<NN, L, PREC_FP32>(
                                uniform_ptr(j.yt + ((size_t)t * j.S + s) * NN), uniform_ptr(j.diag + sN),
-                               uniform_ptr(j.rlat + sN * NN), nullptr, j.P + (size_t)s * j.K * j.NP, j.K,
-                               j.NP, 0, j.permd + sN, j.out + ((size_t)t * j.S + s) * NN, nullptr, sm, sr)))
+                               uniform_ptr(j.rlat + sN * NN), nullptr, j.P + (size_t)s * j.K * j.NP,
+                               j.order ? j.order + (size_t)s * j.K : nullptr, j.K, j.NP, 0, j.permd + sN,
+                               j.out + ((size_t)t * j.S + s) * NN, nullptr, sm, sr)))
         __syncthreads();
     }
 }

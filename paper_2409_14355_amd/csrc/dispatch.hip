@@ -91,6 +91,7 @@ PathArgs path_args(const SlotDev &sd, const float2 *yt, int T, int32_t *out)
     a.rq = nullptr;
     a.permd = sd.permd;
     a.P = sd.P;
+    a.order = sd.order;
     a.out = out;
     a.llr = nullptr;
     a.part = nullptr;

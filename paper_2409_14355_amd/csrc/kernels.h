@@ -21,6 +21,7 @@ struct SlotDev {
     double *wd;            // (S, N)     R_ll^2 from the float64 pivot norm
     int32_t *permd;        // (S, N)     original user detected at depth d
     uint8_t *P;            // (S, K, NP) ranks 1..|Q| per depth, padded with 1
+    uint16_t *order;       // (S, K)     path run by each lane (K <= 256), else null
     uint32_t *rec;         // (S, N, K)  position-set back pointers when they do not fit in LDS
 };
 
@@ -31,6 +32,7 @@ struct JobDev {
     const float4 *diag;
     const int32_t *permd;
     const uint8_t *P;
+    const uint16_t *order;
     int32_t *out;          // (T, S, N)
     int S, T, N, K, NP;
     int item_begin;        // first global work item of this job

@@ -68,6 +68,45 @@ __device__ __forceinline__ void bitonic_finish(double (&cs)[E], uint32_t (&cp)[E
     }
 }
 
+// Full ascending bitonic sort of 64 E entries (entry g = j * 64 + lane).
+template <int E>
+__device__ __forceinline__ void bitonic_sort_full(double (&cs)[E], uint32_t (&cp)[E], int lane)
+{
+    constexpr int KP = 64 * E;
+#pragma unroll
+    for (int size = 2; size <= KP; size <<= 1) {
+#pragma unroll
+        for (int stride = size / 2; stride >= 1; stride >>= 1) {
+            if (stride >= 64) {
+                const int js = stride / 64;
+#pragma unroll
+                for (int j = 0; j < E; ++j)
+                    if ((j & js) == 0) {
+                        const bool asc = ((j * 64) & size) == 0;
+                        const double ls = cs[j], hs = cs[j + js];
+                        const uint32_t lp = cp[j], hp = cp[j + js];
+                        const bool sw = asc == key_lt(hs, hp, ls, lp);
+                        cs[j] = sw ? hs : ls;
+                        cp[j] = sw ? hp : lp;
+                        cs[j + js] = sw ? ls : hs;
+                        cp[j + js] = sw ? lp : hp;
+                    }
+            } else {
+                const bool lower = (lane & stride) == 0;
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    const bool asc = ((j * 64 + lane) & size) == 0;
+                    const double os = __shfl_xor(cs[j], stride);
+                    const uint32_t op = __shfl_xor(cp[j], stride);
+                    const bool take = (lower == asc) == key_lt(os, op, cs[j], cp[j]);
+                    cs[j] = take ? os : cs[j];
+                    cp[j] = take ? op : cp[j];
+                }
+            }
+        }
+    }
+}
+
 template <int E>
 __global__ __launch_bounds__(64) void posvec_reg_kernel(PosArgs a)
 {
@@ -204,18 +243,30 @@ __global__ __launch_bounds__(64) void posvec_reg_kernel(PosArgs a)
         __syncthreads();
     }
 
-    // rebuild the position vectors (ranks 1..|Q|), rows padded with 1
+    // rebuild the position vectors (ranks 1..|Q|), rows padded with 1, and
+    // note for each which depths ask for a rank >= 3 and >= 2
     const int nw = a.NP >> 2;
-    for (int r = lane; r < K; r += 64) {
+    double ks[E];
+    uint32_t kr[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int r = j * 64 + lane;
+        ks[j] = INF;
+        kr[j] = (uint32_t)r << 12;
+        if (r >= K)
+            continue;
         uint32_t wv[kMaxN / 4];
 #pragma unroll
         for (int w = 0; w < kMaxN / 4; ++w)
             wv[w] = 0x01010101u;
+        uint32_t m3 = 0, m2 = 0;
         int pidx = r;
         for (int d = N - 1; d >= 0; --d) {
             const uint32_t e = rec[(size_t)d * KP + pidx];
             const uint32_t pk = (e >> 16) + 1u;
             pidx = (int)(e & 0xffffu);
+            m3 |= (pk >= 3u ? 1u : 0u) << d;
+            m2 |= (pk >= 2u ? 1u : 0u) << d;
 #pragma unroll
             for (int w = 0; w < kMaxN / 4; ++w)
                 if (w == (d >> 2))
@@ -226,6 +277,22 @@ __global__ __launch_bounds__(64) void posvec_reg_kernel(PosArgs a)
         for (int w = 0; w < kMaxN / 4; ++w)
             if (w < nw)
                 dst[w] = wv[w];
+        // sort key: depths with rank >= 3 first, then depths with rank >= 2
+        // (as a double the low bits of the second mask may round; the key
+        // only groups paths, any order is correct)
+        ks[j] = (double)m3 * 4294967296.0 + (double)m2;
+    }
+    // Lane order: paths sorted by that key, so that the lanes of one
+    // wavefront need the costly point choices at the same depths.
+    // order[i] = path run by lane i.
+    if (a.order != nullptr) {
+        bitonic_sort_full<E>(ks, kr, lane);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int g = j * 64 + lane;
+            if (g < K)
+                a.order[(size_t)s * K + g] = (uint16_t)(kr[j] >> 12);
+        }
     }
 }
 

@@ -527,6 +527,7 @@ hipError_t launch_posvec(const SlotDev &sd, hipStream_t st)
     a.NP = sd.NP;
     a.P = sd.P;
     a.rec_g = sd.rec;
+    a.order = sd.order;
     if (sd.K <= 256)
         return launch_posvec_reg(a, st);
     const bool in_lds = posvec_rec_fits_lds(sd.N, sd.K);

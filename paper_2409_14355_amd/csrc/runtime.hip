@@ -236,7 +236,7 @@ int validate_shape(int S, int M, int N, int mod, int n_paths)
 
 // Offsets of the slot arrays inside one pool block.
 struct SlotLayout {
-    size_t Qd, roff, rlat, rlat_h, rlat_b, diag, wd, permd, P, rec, total;
+    size_t Qd, roff, rlat, rlat_h, rlat_b, diag, wd, permd, P, order, rec, total;
 };
 
 SlotLayout slot_layout(int S, int M, int N, int K, int NP, bool rec_global)
@@ -257,6 +257,7 @@ SlotLayout slot_layout(int S, int M, int N, int K, int NP, bool rec_global)
     put(L.wd, (size_t)S * N * sizeof(double));
     put(L.permd, (size_t)S * N * sizeof(int32_t));
     put(L.P, (size_t)S * K * NP);
+    put(L.order, K <= 256 ? (size_t)S * K * sizeof(uint16_t) : 0);
     put(L.rec, rec_global ? (size_t)S * N * K * sizeof(uint32_t) : 0);
     L.total = o;
     return L;
@@ -295,6 +296,7 @@ int prepare_impl(mpnl_ctx *ctx, const void *H, int S, int M, int N, int mod, int
     sd.wd = (double *)(base + L.wd);
     sd.permd = (int32_t *)(base + L.permd);
     sd.P = (uint8_t *)(base + L.P);
+    sd.order = K <= 256 ? (uint16_t *)(base + L.order) : nullptr;
     sd.rec = rec_global ? (uint32_t *)(base + L.rec) : nullptr;
     slot->block = blk;
     slot->stream = st;
@@ -713,6 +715,7 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
                     J.diag = sd.diag;
                     J.permd = sd.permd;
                     J.P = sd.P;
+                    J.order = sd.order;
                     J.out = jobs[i].out;
                     J.S = sd.S;
                     J.T = jobs[i].T;
