@@ -31,6 +31,11 @@ WORKLOADS = {
     "24x24-qam16-kron-S3276-T14": (24, 24, 4, 3276, 14, 18.0, "kron", 256),
 }
 PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2}
+DTYPES = {"fp32": "f32", "fp16": "f16-operands/f32-accumulate", "bf16": "bf16-operands/f32-accumulate"}
+# uneven multi-cell batch: 40 cells, users U{4..32}, antennas U{users..32},
+# modulation uniform over QPSK/16-QAM/64-QAM, subcarriers U{300..3276},
+# 14 symbols, i.i.d. Rayleigh, 20 dB, paths from {64, 128, 256}
+CELLS_WORKLOAD = "cells40-U4-32-S300-3276-T14"
 
 
 def path_flops_per_vector(N: int, K: int) -> int:
@@ -62,7 +67,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="16x16-qam16-S1200-T14", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="16x16-qam16-S1200-T14",
+                    choices=sorted(WORKLOADS) + [CELLS_WORKLOAD])
+    ap.add_argument("--no-autotune", action="store_true", help="batch workload: default grid sizes")
     ap.add_argument("--paths", type=int, default=0)
     ap.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -74,6 +81,9 @@ def main() -> int:
         print("bench.py measures one GPU: this build has no multi-GPU path (independent "
               "subcarriers/cells would shard across GPUs without communication)", file=sys.stderr)
         return 2
+
+    if args.workload == CELLS_WORKLOAD:
+        return run_cells(args)
 
     import numpy as np
     import torch
@@ -142,8 +152,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16": "f16-operands/f32-accumulate",
-                  "bf16": "bf16-operands/f32-accumulate"}[args.precision],
+        "dtype": DTYPES[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload, "users": N, "antennas": M, "bits_per_symbol": bits,
                    "subcarriers": S, "symbols": T, "n_paths": Kc, "snr_db": snr, "channel": ch,
@@ -161,6 +170,120 @@ def main() -> int:
     if not args.no_cpu_baseline:
         n_sub = args.cpu_subcarriers or min(S, {4: 64, 16: 1200, 24: 1000}.get(N, 200))
         res["cpu_baseline"] = cpu_baseline(sl, bits, Kc, n_sub)
+    ctx.close()
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def run_cells(args) -> int:
+    """Forty uneven cells detected as one planned batch (graph replay)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2409_14355_amd as mp
+    import synth
+
+    T, snr = 14, 20.0
+    cells = synth.draw_cells(40, seed=(2, 0))
+    dev = torch.device("cuda:0")
+    slots, jobs = [], []
+    for i, c in enumerate(cells):
+        sl = synth.make_slot(S=c.S, T=T, M=c.M, N=c.N, bits=c.bits, snr_db=snr, seed=(2, 1, i))
+        slots.append(sl)
+        jobs.append(dict(H=torch.from_numpy(sl.H).to(dev), y=torch.from_numpy(sl.y).to(dev),
+                         mod=c.bits, n_paths=c.n_paths,
+                         out=torch.empty((T, c.S, c.N), dtype=torch.int32, device=dev)))
+    Ks = [min(c.n_paths, (1 << c.bits) ** c.N) for c in cells]
+    nvec = sum(c.S for c in cells) * T
+    ctx = mp.Context(0)
+    ctx.set_precision(PRECISIONS[args.precision])
+    plan = ctx.batch_plan([dict(S=c.S, T=T, M=c.M, N=c.N, mod=c.bits, n_paths=c.n_paths) for c in cells],
+                          autotune=not args.no_autotune)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(args.warmup, 1)):
+        plan.run(jobs)
+    torch.cuda.synchronize()
+    errs = sum(synth.bit_errors(j["out"].cpu().numpy(), sl.s_idx, sl.bits) for j, sl in zip(jobs, slots))
+    ber = errs / sum(sl.s_idx.size * sl.bits for sl in slots)
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        plan.run(jobs)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    value = nvec * args.steps / wall
+
+    # stage breakdown of the same launches, enqueued one by one with timers
+    ctx.profile(True)
+    ctx.profile_collect()
+    n_prof = 5
+    for _ in range(n_prof):
+        plan.run(jobs)
+    torch.cuda.synchronize()
+    prof = ctx.profile_collect()
+    ctx.profile(False)
+    stages = {k: round(v[0] / n_prof, 5) for k, v in prof.items()}
+    paths_ms, paths_n = prof["paths"]
+    flops_run = sum(c.S * T * path_flops_per_vector(c.N, K) for c, K in zip(cells, Ks))
+    achieved = flops_run / (paths_ms / n_prof * 1e-3) / 1e12
+
+    # the plain FP32 kernel on the same jobs, one detect call per cell
+    ctx.set_precision(0)
+    plain_steps = max(3, args.steps // 10)
+    for j in jobs:
+        ctx.detect(j["H"], j["y"], j["mod"], j["n_paths"], j["out"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(plain_steps):
+        for j in jobs:
+            ctx.detect(j["H"], j["y"], j["mod"], j["n_paths"], j["out"])
+    torch.cuda.synchronize()
+    plain = nvec * plain_steps / (time.perf_counter() - t0)
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "vectors/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[args.precision], "data": "synthetic",
+        "config": {"workload": CELLS_WORKLOAD, "cells": len(cells), "symbols": T, "snr_db": snr,
+                   "precision": args.precision,
+                   "channel": "iid", "vectors_per_step": nvec,
+                   "shapes": [[c.N, c.M, c.bits, c.S, K] for c, K in zip(cells, Ks)],
+                   "autotune": not args.no_autotune},
+        "p50_step_ms": float(np.percentile(step_ms, 50)),
+        "p99_step_ms": float(np.percentile(step_ms, 99)),
+        "detected_mbit_per_s": value * sum(c.S * c.N * c.bits for c in cells) / sum(c.S for c in cells) / 1e6,
+        "plain_fp32_per_cell_vectors_per_s": plain,
+        "speedup_vs_plain": value / plain,
+        "ber": ber,
+        "path_launch_shapes": [[x["N"], x["mod"], x["threads"], x["chunk"], x["grid"]]
+                               for x in plan.launch_shapes()],
+        "stage_ms_per_step": stages,
+        "roofline": {"bound": "alu", "kernel": "path_search_batch_kernel", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": None, "flops_per_step": flops_run,
+                     "path_ms_per_step": paths_ms / n_prof, "path_launches_per_step": paths_n / n_prof},
+    }
+    if not args.no_cpu_baseline:
+        n_sub = args.cpu_subcarriers or 24
+        cores = os.cpu_count() or 1
+        t0 = time.perf_counter()
+        nv = 0
+        for sl, K in zip(slots, Ks):
+            oracle.detect_slot("mpnl", sl.H[:n_sub], np.ascontiguousarray(sl.y[:, :n_sub]), sl.bits,
+                               n_paths=K, nthreads=cores)
+            nv += T * n_sub
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": nv / dt, "unit": "vectors/s", "cores": cores, "kind": "oracle",
+                               "sample": f"first {n_sub} subcarriers x {T} symbols of each of the "
+                                         f"{len(cells)} cells ({nv} vectors, {dt:.1f} s wall)"}
+    plan.close()
     ctx.close()
     print(json.dumps(res), flush=True)
     return 0

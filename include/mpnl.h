@@ -199,13 +199,61 @@ typedef struct mpnl_job {
     int n_paths;
 } mpnl_job;
 
-/* Detect several independent jobs (cells) of different shapes with one
-   batched launch per stage: the path searches of every job run in a single
-   persistent kernel that pulls (job, subcarrier, symbol) work items from a
-   device queue.  Each job's result is identical to mpnl_detect() on it alone.
-   Errors: as mpnl_detect() for any job; nothing is enqueued on error. */
+/* Detect several independent jobs (cells) of different shapes: the sorted
+   QR, position sets and rotation run per job, then the path searches of all
+   jobs with the same user count, modulation and workgroup size run in one
+   launch over their (job, subcarrier, symbol) work items; a job with more
+   than 256 paths runs its own path search.  Each job's result is identical
+   to mpnl_detect() on it alone, in the context's precision.  Errors: as
+   mpnl_detect() for any job (shape errors are found before anything is
+   enqueued); MPNL_E_NOMEM / MPNL_E_HIP may leave earlier jobs done. */
 int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs,
                       void *stream);
+
+/* ---- planned batch: fixed shapes, one graph replay per run ------------------- */
+
+typedef struct mpnl_batch mpnl_batch;
+
+/* flags of mpnl_batch_create */
+#define MPNL_BATCH_AUTOTUNE 1u  /* on the first run, time candidate launch
+                                   shapes (items per workgroup step, grid
+                                   size) of every path-search launch and keep
+                                   the fastest before capturing              */
+
+/* Plan an uneven multi-cell batch whose job shapes (S, T, M, N, mod, n_paths;
+   the pointers are ignored) stay fixed across runs.  Allocates every job's
+   slot state and workspace once from the context budget and groups the jobs
+   into batched launches: sorted QR per antenna-count bucket, position sets
+   per path-count bucket, one rotation launch, and one path-search launch per
+   (user count, modulation, workgroup size).  The first
+   mpnl_batch_run() captures the sequence (job-table upload + launches) into
+   HIP graphs that later runs replay.  Every job needs n_paths clamped to
+   <= 256.  Errors: as mpnl_detect() for any job, MPNL_E_UNSUPPORTED for more
+   than 256 paths, MPNL_E_NOMEM.  The path metrics use the precision the
+   context has when the batch is created; mpnl_destroy() frees batches
+   still open. */
+int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs,
+                      unsigned flags, mpnl_batch **batch);
+
+/* Detect a planned batch on new buffers: `jobs` must have the planned shapes
+   in the planned order; only H, y and out are read from it.  Enqueues one
+   graph launch on `stream`.  Runs of one batch share its workspace: order
+   them on one stream.  Errors: MPNL_E_INVAL (null, shape mismatch),
+   MPNL_E_HIP. */
+int mpnl_batch_run(mpnl_ctx *ctx, mpnl_batch *batch, const mpnl_job *jobs,
+                   void *stream);
+
+/* Launch shapes of the batch's path-search launches: n_launches receives
+   their number; shapes (room for max launches, 5 ints each) receives per
+   launch {N, mod, workgroup size, chunk, grid}: the launch's workgroups take
+   `chunk` consecutive (job, subcarrier, symbol) items per step, strided by
+   grid * chunk (a persistent grid when grid * chunk is below the items).
+   Errors: MPNL_E_INVAL for a null batch or negative max. */
+int mpnl_batch_info(const mpnl_batch *batch, int *n_launches, int *shapes,
+                    int max);
+
+/* Free a batch (waits for its runs).  NULL is accepted. */
+int mpnl_batch_destroy(mpnl_ctx *ctx, mpnl_batch *batch);
 
 #ifdef __cplusplus
 }

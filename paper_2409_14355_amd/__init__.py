@@ -34,7 +34,9 @@ EXPORTED = (
     "mpnl_set_precision", "mpnl_memory_usage", "mpnl_detect", "mpnl_slot_prepare",
     "mpnl_slot_detect", "mpnl_slot_detect_soft", "mpnl_slot_release", "mpnl_slot_export",
     "mpnl_slot_info", "mpnl_detect_batch", "mpnl_profile_enable", "mpnl_profile_collect",
+    "mpnl_batch_create", "mpnl_batch_run", "mpnl_batch_info", "mpnl_batch_destroy",
 )
+MPNL_BATCH_AUTOTUNE = 1
 MPNL_STAGE_SQRD, MPNL_STAGE_POSVEC, MPNL_STAGE_ROTATE, MPNL_STAGE_PATHS = 0, 1, 2, 3
 STAGE_NAMES = ("sqrd", "posvec", "rotate", "paths")
 
@@ -80,6 +82,10 @@ def lib() -> ctypes.CDLL:
     L.mpnl_slot_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.mpnl_slot_info.argtypes = [vp] + [ctypes.POINTER(ip)] * 5
     L.mpnl_detect_batch.argtypes = [vp, ctypes.POINTER(mpnl_job), ip, vp]
+    L.mpnl_batch_create.argtypes = [vp, ctypes.POINTER(mpnl_job), ip, ctypes.c_uint, ctypes.POINTER(vp)]
+    L.mpnl_batch_run.argtypes = [vp, vp, ctypes.POINTER(mpnl_job), vp]
+    L.mpnl_batch_info.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), ip]
+    L.mpnl_batch_destroy.argtypes = [vp, vp]
     L.mpnl_profile_enable.argtypes = [vp, ip]
     L.mpnl_profile_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ip)]
     _lib = L
@@ -191,14 +197,49 @@ def mpnl_slot_info(slot: int) -> dict:
     return dict(zip(("S", "M", "N", "mod", "K"), (x.value for x in v)))
 
 
-def mpnl_detect_batch(ctx: int, jobs: Sequence[dict], stream=None) -> None:
+def _job_array(jobs: Sequence[dict]):
+    """Jobs as dicts {H, y, out, mod, n_paths}; a dict without tensors may give
+    the sizes S, T, M, N directly (shapes of a batch plan)."""
     arr = (mpnl_job * len(jobs))()
     for i, j in enumerate(jobs):
-        S, M, N = j["H"].shape
-        T = j["y"].shape[0]
-        arr[i] = mpnl_job(_ptr(j["H"]), _ptr(j["y"]), _ptr(j["out"]), S, T, M, N, j["mod"],
-                          j["n_paths"])
+        if "H" in j:
+            S, M, N = j["H"].shape
+            T = j["y"].shape[0]
+        else:
+            S, T, M, N = j["S"], j["T"], j["M"], j["N"]
+        arr[i] = mpnl_job(_ptr(j.get("H")), _ptr(j.get("y")), _ptr(j.get("out")), S, T, M, N,
+                          j["mod"], j["n_paths"])
+    return arr
+
+
+def mpnl_detect_batch(ctx: int, jobs: Sequence[dict], stream=None) -> None:
+    arr = _job_array(jobs)
     _check(lib().mpnl_detect_batch(ctx, arr, len(jobs), _stream(stream)), "mpnl_detect_batch")
+
+
+def mpnl_batch_create(ctx: int, shapes: Sequence[dict], flags: int = 0) -> int:
+    arr = _job_array(shapes)
+    h = ctypes.c_void_p()
+    _check(lib().mpnl_batch_create(ctx, arr, len(shapes), flags, ctypes.byref(h)), "mpnl_batch_create")
+    return h.value
+
+
+def mpnl_batch_run(ctx: int, batch: int, jobs: Sequence[dict], stream=None) -> None:
+    arr = _job_array(jobs)
+    _check(lib().mpnl_batch_run(ctx, batch, arr, _stream(stream)), "mpnl_batch_run")
+
+
+def mpnl_batch_info(batch: int, max_launches: int = 128) -> list[dict]:
+    """-> launch shape of every path-search launch of the plan."""
+    n = ctypes.c_int()
+    v = (ctypes.c_int * (5 * max_launches))()
+    _check(lib().mpnl_batch_info(batch, ctypes.byref(n), v, max_launches), "mpnl_batch_info")
+    keys = ("N", "mod", "threads", "chunk", "grid")
+    return [dict(zip(keys, v[5 * i:5 * i + 5])) for i in range(min(n.value, max_launches))]
+
+
+def mpnl_batch_destroy(ctx: int, batch: int) -> None:
+    _check(lib().mpnl_batch_destroy(ctx, batch), "mpnl_batch_destroy")
 
 
 def mpnl_profile_enable(ctx: int, enable: bool) -> None:
@@ -319,6 +360,32 @@ class Context:
                 j["out"] = torch.empty((T, S, N), dtype=torch.int32, device=j["H"].device)
         mpnl_detect_batch(self.handle, jobs, stream)
         return [j["out"] for j in jobs]
+
+    def batch_plan(self, shapes: Sequence[dict], autotune: bool = False) -> "BatchPlan":
+        return BatchPlan(self, shapes, autotune)
+
+
+class BatchPlan:
+    """A fixed set of job shapes whose whole pipeline (every stage of every
+    job) replays as one captured graph; each run takes new tensors of the
+    same shapes."""
+
+    def __init__(self, ctx: Context, shapes: Sequence[dict], autotune: bool = False):
+        self.ctx = ctx
+        self.shapes = [dict(s) for s in shapes]
+        self.handle = mpnl_batch_create(ctx.handle, self.shapes, MPNL_BATCH_AUTOTUNE if autotune else 0)
+
+    def run(self, jobs: Sequence[dict], stream=None):
+        mpnl_batch_run(self.ctx.handle, self.handle, jobs, stream)
+        return [j["out"] for j in jobs]
+
+    def launch_shapes(self) -> list[dict]:
+        return mpnl_batch_info(self.handle)
+
+    def close(self):
+        if self.handle and self.ctx.handle:
+            mpnl_batch_destroy(self.ctx.handle, self.handle)
+        self.handle = 0
 
 
 _default_ctx: Optional[Context] = None

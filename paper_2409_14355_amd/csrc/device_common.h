@@ -67,6 +67,33 @@ struct PosArgs {
     uint32_t *rec_g;  // (S, N, K) when the back pointers do not fit in LDS
 };
 
+// One job of a batched launch of a1 / a2 / a3 (slot state and workspace of
+// the job, its input and the first work item of the job in the launch).
+struct StageJob {
+    const float2 *H;  // (S, M, N)
+    const float2 *y;  // (T, S, M)
+    float2 *yt;       // (T, S, N)
+    SlotDev sd;
+    int T;
+    float delta;
+    int item_begin;
+};
+
+// index of the job owning work item `item` (jobs sorted by item_begin)
+template <typename J>
+__device__ __forceinline__ int find_job(const J *jobs, int n_jobs, int item)
+{
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].item_begin <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 // ============================================================================
 // a4: choice of the k-th closest constellation point at one depth, in lattice
 // units.  Level index m in 0..L-1 <-> level value 2m - (L-1).
@@ -599,51 +626,41 @@ __global__ __launch_bounds__(256) void path_search_soft_kernel(PathArgs a)
 }
 
 // ============================================================================
-// Batched path search: one persistent launch for many jobs (cells) of one
-// (user-count bucket, modulation).  Workgroups take (job, subcarrier,
-// symbol) items from a device counter until the queue is empty; each item is
-// processed exactly as path_search_kernel processes it, so the result of a
-// job does not depend on the other jobs in the batch.
+// Path search over many jobs (cells) that share the user count N and the
+// modulation.  Work items are (job, subcarrier, symbol), numbered job by job;
+// workgroup b takes chunks of `chunk` consecutive items: chunk b, b + grid,
+// b + 2 grid, ... (a persistent, statically strided grid when grid * chunk
+// is below the item count).  Each item is processed exactly as
+// path_search_kernel processes it, so a job's result does not depend on the
+// other jobs of the launch.
 // ============================================================================
-struct BatchArgs {
+struct MultiArgs {
     const JobDev *jobs;
-    int n_jobs, total_items;
-    unsigned *counter;
+    int n_jobs, total_items, chunk;
 };
 
-template <int NMAX, int L>
-__global__ __launch_bounds__(256) void path_search_batch_kernel(BatchArgs a)
+template <int N, int L, int PREC>
+__global__ __launch_bounds__(256) void path_search_multi_kernel(MultiArgs a)
 {
-    __shared__ int item_s;
     __shared__ float sm[4];
     __shared__ int sr[4];
-    for (;;) {
-        if (threadIdx.x == 0)
-            item_s = (int)atomicAdd(a.counter, 1u);
-        __syncthreads();
-        const int item = item_s;
-        __syncthreads();
-        if (item >= a.total_items)
-            break;
-        int lo = 0, hi = a.n_jobs - 1;  // job owning the item (jobs sorted by item_begin)
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.jobs[mid].item_begin <= item)
-                lo = mid;
-            else
-                hi = mid - 1;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int stride = gridDim.x * a.chunk;
+    for (int i0 = lb * a.chunk; i0 < a.total_items; i0 += stride) {
+        const int i1 = min(i0 + a.chunk, a.total_items);
+        for (int item = i0; item < i1; ++item) {
+            const JobDev &j = a.jobs[find_job(a.jobs, a.n_jobs, item)];
+            const int li = item - j.item_begin;
+            const int s = li / j.T, t = li - s * j.T;
+            const size_t sN = (size_t)s * N;
+            const size_t v = (size_t)t * j.S + s;
+            cptr<uint32_t> rq = j.rq ? uniform_ptr(j.rq + sN * N) : nullptr;
+            search_vector<N, L, PREC>(uniform_ptr(j.yt + v * N), uniform_ptr(j.diag + sN),
+                                      uniform_ptr(j.rlat + sN * N), rq, j.P + (size_t)s * j.K * j.NP,
+                                      j.order ? j.order + (size_t)s * j.K : nullptr, j.K, j.NP, 0,
+                                      j.permd + sN, j.out + v * N, nullptr, sm, sr);
+            __syncthreads();
         }
-        const JobDev j = a.jobs[lo];
-        const int li = item - j.item_begin;
-        const int s = li / j.T, t = li - s * j.T;
-        const size_t sN = (size_t)s * j.N;
-        MPNL_BUCKET_SWITCH(NMAX, j.N,
-                           (search_vector<NN, L, PREC_FP32>(
-                               uniform_ptr(j.yt + ((size_t)t * j.S + s) * NN), uniform_ptr(j.diag + sN),
-                               uniform_ptr(j.rlat + sN * NN), nullptr, j.P + (size_t)s * j.K * j.NP,
-                               j.order ? j.order + (size_t)s * j.K : nullptr, j.K, j.NP, 0, j.permd + sN,
-                               j.out + ((size_t)t * j.S + s) * NN, nullptr, sm, sr)))
-        __syncthreads();
     }
 }
 

@@ -39,10 +39,39 @@ hipError_t soft_launch_nmax8(const dev::PathArgs &, int, hipStream_t);
 hipError_t soft_launch_nmax16(const dev::PathArgs &, int, hipStream_t);
 hipError_t soft_launch_nmax24(const dev::PathArgs &, int, hipStream_t);
 hipError_t soft_launch_nmax32(const dev::PathArgs &, int, hipStream_t);
-hipError_t batch_launch_nmax8(const dev::BatchArgs &, int, int, int, hipStream_t);
-hipError_t batch_launch_nmax16(const dev::BatchArgs &, int, int, int, hipStream_t);
-hipError_t batch_launch_nmax24(const dev::BatchArgs &, int, int, int, hipStream_t);
-hipError_t batch_launch_nmax32(const dev::BatchArgs &, int, int, int, hipStream_t);
+
+hipError_t path_multi_launch_n1(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n2(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n3(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n4(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n5(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n6(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n7(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n8(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n9(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n10(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n11(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n12(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n13(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n14(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n15(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n16(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n17(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n18(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n19(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n20(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n21(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n22(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n23(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n24(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n25(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n26(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n27(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n28(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n29(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n30(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n31(const dev::MultiArgs &, int, int, int, int, hipStream_t);
+hipError_t path_multi_launch_n32(const dev::MultiArgs &, int, int, int, int, hipStream_t);
 
 namespace {
 using namespace dev;
@@ -81,6 +110,42 @@ const PathLaunch kPathLaunch[32] = {
     path_launch_n30,
     path_launch_n31,
     path_launch_n32};
+
+typedef hipError_t (*MultiLaunch)(const MultiArgs &, int, int, int, int, hipStream_t);
+const MultiLaunch kMultiLaunch[32] = {
+    path_multi_launch_n1,
+    path_multi_launch_n2,
+    path_multi_launch_n3,
+    path_multi_launch_n4,
+    path_multi_launch_n5,
+    path_multi_launch_n6,
+    path_multi_launch_n7,
+    path_multi_launch_n8,
+    path_multi_launch_n9,
+    path_multi_launch_n10,
+    path_multi_launch_n11,
+    path_multi_launch_n12,
+    path_multi_launch_n13,
+    path_multi_launch_n14,
+    path_multi_launch_n15,
+    path_multi_launch_n16,
+    path_multi_launch_n17,
+    path_multi_launch_n18,
+    path_multi_launch_n19,
+    path_multi_launch_n20,
+    path_multi_launch_n21,
+    path_multi_launch_n22,
+    path_multi_launch_n23,
+    path_multi_launch_n24,
+    path_multi_launch_n25,
+    path_multi_launch_n26,
+    path_multi_launch_n27,
+    path_multi_launch_n28,
+    path_multi_launch_n29,
+    path_multi_launch_n30,
+    path_multi_launch_n31,
+    path_multi_launch_n32,
+};
 
 PathArgs path_args(const SlotDev &sd, const float2 *yt, int T, int32_t *out)
 {
@@ -162,21 +227,17 @@ hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, f
     }
 }
 
-hipError_t launch_path_search_batch(const JobDev *jobs_dev, int n_jobs, int total_items,
-                                    int nmax_bkt, int bits, int threads, unsigned *counter,
-                                    int grid, hipStream_t st)
+hipError_t launch_path_search_multi(const JobDev *jobs_dev, int n_jobs, int total_items, int N, int bits,
+                                    int precision, int threads, int chunk, int grid, hipStream_t st)
 {
-    BatchArgs a;
+    if (N < 1 || N > 32 || chunk < 1 || grid < 1 || threads < 64 || threads > 256 || threads % 64)
+        return hipErrorInvalidValue;
+    MultiArgs a;
     a.jobs = jobs_dev;
     a.n_jobs = n_jobs;
     a.total_items = total_items;
-    a.counter = counter;
-    switch (nmax_bkt) {
-    case 8: return batch_launch_nmax8(a, bits, threads, grid, st);
-    case 16: return batch_launch_nmax16(a, bits, threads, grid, st);
-    case 24: return batch_launch_nmax24(a, bits, threads, grid, st);
-    default: return batch_launch_nmax32(a, bits, threads, grid, st);
-    }
+    a.chunk = chunk;
+    return kMultiLaunch[N - 1](a, bits, precision, threads, grid, st);
 }
 
 }  // namespace mpnl

@@ -29,6 +29,7 @@ struct SlotDev {
 struct JobDev {
     const float2 *yt;      // (T, S, N) rotated received vectors, depth order, lattice units
     const float2 *rlat;
+    const uint32_t *rq;    // packed FP16 / BF16 copy of rlat for reduced precision, else null
     const float4 *diag;
     const int32_t *permd;
     const uint8_t *P;
@@ -51,9 +52,22 @@ hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_
 hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, float sigma2,
                                    float clip, float *llr, int32_t *out, hipStream_t st);
 // Batched path search over many jobs sharing (NMAX bucket, bits); one persistent launch.
-hipError_t launch_path_search_batch(const JobDev *jobs_dev, int n_jobs, int total_items,
-                                    int nmax_bucket, int bits, int max_threads,
-                                    unsigned *queue_counter, int grid, hipStream_t st);
+// Path search of many jobs with the same N and modulation (each with
+// n_paths <= 256; threads = n_paths rounded up to 64), chunk consecutive
+// items per workgroup step, `grid` workgroups.
+hipError_t launch_path_search_multi(const JobDev *jobs_dev, int n_jobs, int total_items, int N, int bits,
+                                    int precision, int threads, int chunk, int grid, hipStream_t st);
+
+namespace dev {
+struct StageJob;
+}
+// Batched a1 / a2 / a3 over a device table of jobs sorted by item_begin
+// (items: subcarrier pairs for a1, subcarriers for a2 and a3).
+hipError_t launch_sqrd_batch(const dev::StageJob *jobs, int n_jobs, int items, int mmax, hipStream_t st);
+hipError_t launch_posvec_batch(const dev::StageJob *jobs, int n_jobs, int items, int E, int Nmax,
+                               hipStream_t st);
+hipError_t launch_rotate_batch(const dev::StageJob *jobs, int n_jobs, int items, hipStream_t st);
+size_t posvec_reg_lds_bytes(int N, int K);
 
 size_t posvec_lds_bytes(int N, int K, bool rec_in_lds);
 bool posvec_rec_fits_lds(int N, int K);

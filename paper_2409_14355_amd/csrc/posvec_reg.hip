@@ -108,16 +108,14 @@ __device__ __forceinline__ void bitonic_sort_full(double (&cs)[E], uint32_t (&cp
 }
 
 template <int E>
-__global__ __launch_bounds__(64) void posvec_reg_kernel(PosArgs a)
+__device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned char *smem)
 {
     constexpr int KP = 64 * E;
     constexpr double INF = (double)INFINITY;
-    extern __shared__ __align__(16) unsigned char smem[];
     double *scA = (double *)smem;             // KP: scores of list A by position
     uint32_t *cnt = (uint32_t *)(scA + KP);  // KP: children per parent rank
     uint32_t *rec = cnt + KP;                 // N * KP: (parent, k) per depth
     const int lane = threadIdx.x;
-    const int s = blockIdx.x;
     const int K = a.K, N = a.N, nq = a.nq;
     const int jK = (K - 1) >> 6, lK = (K - 1) & 63;  // slot of entry K-1
 
@@ -296,6 +294,33 @@ __global__ __launch_bounds__(64) void posvec_reg_kernel(PosArgs a)
     }
 }
 
+template <int E>
+__global__ __launch_bounds__(64) void posvec_reg_kernel(PosArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    posvec_body<E>(a, blockIdx.x, smem);
+}
+
+// One launch for the position sets of many jobs (all with N_p <= 64 E):
+// workgroup b runs subcarrier b - item_begin of the job that owns item b.
+template <int E>
+__global__ __launch_bounds__(64) void posvec_batch_kernel(const StageJob *jobs, int n_jobs)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const StageJob &j = jobs[find_job(jobs, n_jobs, blockIdx.x)];
+    PosArgs a;
+    a.w = j.sd.wd;
+    a.S = j.sd.S;
+    a.N = j.sd.N;
+    a.nq = 1 << j.sd.bits;
+    a.K = j.sd.K;
+    a.NP = j.sd.NP;
+    a.P = j.sd.P;
+    a.rec_g = nullptr;
+    a.order = j.sd.order;
+    posvec_body<E>(a, blockIdx.x - j.item_begin, smem);
+}
+
 }  // namespace
 }  // namespace dev
 
@@ -303,6 +328,22 @@ size_t posvec_reg_lds_bytes(int N, int K)
 {
     const int KP = K <= 64 ? 64 : K <= 128 ? 128 : 256;
     return (size_t)KP * (sizeof(double) + sizeof(uint32_t)) + (size_t)N * KP * sizeof(uint32_t);
+}
+
+hipError_t launch_posvec_batch(const dev::StageJob *jobs, int n_jobs, int items, int E, int Nmax,
+                               hipStream_t st)
+{
+    using namespace dev;
+    const size_t lds = posvec_reg_lds_bytes(Nmax, 64 * E);
+    if (E == 1)
+        hipLaunchKernelGGL(posvec_batch_kernel<1>, dim3(items), dim3(64), lds, st, jobs, n_jobs);
+    else if (E == 2)
+        hipLaunchKernelGGL(posvec_batch_kernel<2>, dim3(items), dim3(64), lds, st, jobs, n_jobs);
+    else if (E == 4)
+        hipLaunchKernelGGL(posvec_batch_kernel<4>, dim3(items), dim3(64), lds, st, jobs, n_jobs);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t launch_posvec_reg(const dev::PosArgs &a, hipStream_t st)

@@ -40,7 +40,7 @@ __device__ __forceinline__ uint32_t bf16_bits(float x)
 }
 
 template <int MMAX>
-__global__ __launch_bounds__(64) void sqrd_kernel(SqrdArgs a)
+__device__ __forceinline__ void sqrd_body(const SqrdArgs &a, int pair)
 {
     __shared__ float2 V[2][kMaxN][MMAX];
     __shared__ float TAU[2][kMaxN];
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(64) void sqrd_kernel(SqrdArgs a)
 
     const int half = threadIdx.x >> 5;
     const int c = threadIdx.x & 31;
-    const int s = blockIdx.x * 2 + half;
+    const int s = pair * 2 + half;
     const int M = a.M, N = a.N;
     const bool active = (s < a.S) && (c < N);
 
@@ -211,6 +211,28 @@ __global__ __launch_bounds__(64) void sqrd_kernel(SqrdArgs a)
             }
         }
     }
+}
+
+template <int MMAX>
+__global__ __launch_bounds__(64) void sqrd_kernel(SqrdArgs a)
+{
+    sqrd_body<MMAX>(a, blockIdx.x);
+}
+
+// One launch for the sorted QRs of many jobs: workgroup b runs subcarrier
+// pair b - item_begin of the job that owns item b.
+template <int MMAX>
+__global__ __launch_bounds__(64) void sqrd_batch_kernel(const StageJob *jobs, int n_jobs)
+{
+    const StageJob &j = jobs[find_job(jobs, n_jobs, blockIdx.x)];
+    SqrdArgs a;
+    a.H = j.H;
+    a.S = j.sd.S;
+    a.M = j.sd.M;
+    a.N = j.sd.N;
+    a.delta = j.delta;
+    a.sd = j.sd;
+    sqrd_body<MMAX>(a, blockIdx.x - j.item_begin);
 }
 
 // ============================================================================
@@ -419,9 +441,8 @@ struct RotArgs {
     int S, M, N, T;
 };
 
-__global__ __launch_bounds__(64) void rotate_kernel(RotArgs a)
+__device__ __forceinline__ void rotate_body(const RotArgs &a, int s)
 {
-    const int s = blockIdx.x;
     const int lane = threadIdx.x;
     const int i16 = lane & 15, kq = lane >> 4;
     const int M = a.M, N = a.N, T = a.T, S = a.S;
@@ -462,6 +483,28 @@ __global__ __launch_bounds__(64) void rotate_kernel(RotArgs a)
 }
 
 
+__global__ __launch_bounds__(64) void rotate_kernel(RotArgs a)
+{
+    rotate_body(a, blockIdx.x);
+}
+
+// One launch for the rotations of many jobs: workgroup b runs subcarrier
+// b - item_begin of the job that owns item b.
+__global__ __launch_bounds__(64) void rotate_batch_kernel(const StageJob *jobs, int n_jobs)
+{
+    const StageJob &j = jobs[find_job(jobs, n_jobs, blockIdx.x)];
+    RotArgs a;
+    a.diag = j.sd.diag;
+    a.Qd = j.sd.Qd;
+    a.y = j.y;
+    a.yt = j.yt;
+    a.S = j.sd.S;
+    a.M = j.sd.M;
+    a.N = j.sd.N;
+    a.T = j.T;
+    rotate_body(a, blockIdx.x - j.item_begin);
+}
+
 template <int MMAX>
 hipError_t sqrd_launch_t(const float2 *H, const SlotDev &sd, hipStream_t st)
 {
@@ -480,6 +523,28 @@ hipError_t sqrd_launch_t(const float2 *H, const SlotDev &sd, hipStream_t st)
 }  // namespace dev
 
 using namespace dev;
+
+hipError_t launch_sqrd_batch(const StageJob *jobs, int n_jobs, int items, int mmax, hipStream_t st)
+{
+    switch (mmax) {
+    case 4: hipLaunchKernelGGL(sqrd_batch_kernel<4>, dim3(items), dim3(64), 0, st, jobs, n_jobs); break;
+    case 8: hipLaunchKernelGGL(sqrd_batch_kernel<8>, dim3(items), dim3(64), 0, st, jobs, n_jobs); break;
+    case 12: hipLaunchKernelGGL(sqrd_batch_kernel<12>, dim3(items), dim3(64), 0, st, jobs, n_jobs); break;
+    case 16: hipLaunchKernelGGL(sqrd_batch_kernel<16>, dim3(items), dim3(64), 0, st, jobs, n_jobs); break;
+    case 20: hipLaunchKernelGGL(sqrd_batch_kernel<20>, dim3(items), dim3(64), 0, st, jobs, n_jobs); break;
+    case 24: hipLaunchKernelGGL(sqrd_batch_kernel<24>, dim3(items), dim3(64), 0, st, jobs, n_jobs); break;
+    case 28: hipLaunchKernelGGL(sqrd_batch_kernel<28>, dim3(items), dim3(64), 0, st, jobs, n_jobs); break;
+    case 32: hipLaunchKernelGGL(sqrd_batch_kernel<32>, dim3(items), dim3(64), 0, st, jobs, n_jobs); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rotate_batch(const StageJob *jobs, int n_jobs, int items, hipStream_t st)
+{
+    hipLaunchKernelGGL(rotate_batch_kernel, dim3(items), dim3(64), 0, st, jobs, n_jobs);
+    return hipGetLastError();
+}
 
 
 

@@ -11,6 +11,7 @@
 #include <new>
 #include <vector>
 
+#include "device_common.h"
 #include "kernels.h"
 
 namespace {
@@ -44,6 +45,7 @@ struct mpnl_ctx {
     int precision = MPNL_PREC_FP32;
     std::vector<Block> blocks;
     std::vector<mpnl_slot *> slots;
+    std::vector<mpnl_batch *> batches;
     void *pinned = nullptr;  // staging for batch job tables
     size_t pinned_size = 0;
     hipEvent_t pinned_ev = nullptr;
@@ -58,6 +60,8 @@ struct mpnl_ctx {
 };
 
 namespace {
+
+void plan_free(mpnl_ctx *ctx, mpnl_batch *p);
 
 class DeviceGuard {
   public:
@@ -234,6 +238,12 @@ int validate_shape(int S, int M, int N, int mod, int n_paths)
     return MPNL_OK;
 }
 
+// Packed reduced-precision copy of the lattice-scaled R for a precision.
+const uint32_t *rq_of(const mpnl::SlotDev &sd, int precision)
+{
+    return precision == MPNL_PREC_FP16 ? sd.rlat_h : precision == MPNL_PREC_BF16 ? sd.rlat_b : nullptr;
+}
+
 // Offsets of the slot arrays inside one pool block.
 struct SlotLayout {
     size_t Qd, roff, rlat, rlat_h, rlat_b, diag, wd, permd, P, order, rec, total;
@@ -398,6 +408,8 @@ int mpnl_destroy(mpnl_ctx *ctx)
     (void)hipDeviceSynchronize();
     for (mpnl_slot *s : ctx->slots)
         delete s;
+    for (mpnl_batch *p : ctx->batches)
+        plan_free(ctx, p);
     for (Block &b : ctx->blocks) {
         if (b.ptr)
             (void)hipFree(b.ptr);
@@ -649,34 +661,34 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
             rc = hip_fail(ctx, e);
     }
 
-    // a4+a5: one persistent launch per (user-count bucket, modulation,
-    // workgroup size = paths rounded up to a wavefront)
+    // a4+a5: one launch per (user count, modulation, workgroup size = paths
+    // rounded up to a wavefront)
     if (rc == MPNL_OK) {
         struct Group {
-            int bucket, bits, threads;
+            int N, bits, threads;
             std::vector<int> idx;
         };
         std::vector<Group> groups;
         for (int i = 0; i < n_jobs; ++i) {
             if (!batched[i])
                 continue;
-            const int bk = mpnl::nmax_bucket(jobs[i].N), bits = jobs[i].mod;
+            const int N = jobs[i].N, bits = jobs[i].mod;
             const int thr = (slots[i]->sd.K + 63) / 64 * 64;
             auto it = std::find_if(groups.begin(), groups.end(), [&](const Group &q) {
-                return q.bucket == bk && q.bits == bits && q.threads == thr;
+                return q.N == N && q.bits == bits && q.threads == thr;
             });
             if (it == groups.end()) {
-                groups.push_back({bk, bits, thr, {}});
+                groups.push_back({N, bits, thr, {}});
                 it = groups.end() - 1;
             }
             it->idx.push_back(i);
         }
-        // job tables of every group, plus one queue counter per group, in one upload
+        // job tables of every group in one upload
         size_t table_bytes = 0;
         std::vector<size_t> goff(groups.size());
         for (size_t q = 0; q < groups.size(); ++q) {
             goff[q] = table_bytes;
-            table_bytes += align_up(groups[q].idx.size() * sizeof(mpnl::JobDev) + sizeof(unsigned) * 4);
+            table_bytes += align_up(groups[q].idx.size() * sizeof(mpnl::JobDev));
         }
         if (ctx->pinned_ev && hipEventSynchronize(ctx->pinned_ev) != hipSuccess)
             rc = MPNL_E_HIP;
@@ -712,6 +724,7 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
                     mpnl::JobDev &J = jd[u];
                     J.yt = (const float2 *)ctx->blocks[ytb[i]].ptr;
                     J.rlat = sd.rlat;
+                    J.rq = rq_of(sd, ctx->precision);
                     J.diag = sd.diag;
                     J.permd = sd.permd;
                     J.P = sd.P;
@@ -725,8 +738,6 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
                     J.item_begin = acc;
                     acc += sd.S * jobs[i].T;
                 }
-                unsigned *cnt = (unsigned *)(host + goff[q] + groups[q].idx.size() * sizeof(mpnl::JobDev));
-                cnt[0] = 0;
                 items[q] = acc;
                 threads[q] = groups[q].threads;
             }
@@ -735,12 +746,9 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
                 e = hipEventRecord(ctx->pinned_ev, st);
             for (size_t q = 0; q < groups.size() && e == hipSuccess; ++q) {
                 const mpnl::JobDev *jd = (const mpnl::JobDev *)(dev + goff[q]);
-                unsigned *cnt = (unsigned *)(dev + goff[q] + groups[q].idx.size() * sizeof(mpnl::JobDev));
-                // enough resident workgroups to fill the 256 CUs, never more than the items
-                const int grid = std::min(items[q], 256 * (threads[q] >= 256 ? 4 : 8));
                 StageTimer tm(ctx, MPNL_STAGE_PATHS, st);
-                e = mpnl::launch_path_search_batch(jd, (int)groups[q].idx.size(), items[q], groups[q].bucket,
-                                                   groups[q].bits, threads[q], cnt, grid, st);
+                e = mpnl::launch_path_search_multi(jd, (int)groups[q].idx.size(), items[q], groups[q].N,
+                                                   groups[q].bits, ctx->precision, threads[q], 1, items[q], st);
             }
             if (e != hipSuccess)
                 rc = hip_fail(ctx, e);
@@ -754,6 +762,463 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
             release_impl(ctx, slots[i]);
     }
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Planned batch
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+enum LaunchKind { L_SQRD = 0, L_POSVEC = 1, L_ROTATE = 2, L_PATHS = 3 };
+
+struct PlanLaunch {
+    int kind;
+    int param;        // a1: MMAX; a2: E; a4: user count N
+    int bits;         // a4
+    int threads;      // a4 workgroup size
+    int nmax;         // a2: largest N (LDS size)
+    int chunk;        // a4: items per workgroup step (tuned)
+    int grid;         // a4: workgroups (tuned; below items / chunk = persistent)
+    int items;
+    size_t off;       // byte offset of the job table in a table buffer
+    std::vector<int> jobs;
+};
+
+constexpr int kGraphCopies = 2;
+
+}  // namespace
+
+struct mpnl_batch {
+    std::vector<mpnl_job> shapes;
+    std::vector<mpnl::SlotDev> sd;
+    std::vector<float2 *> yt;
+    std::vector<PlanLaunch> launches;
+    int block = -1;
+    size_t table_bytes = 0;
+    void *pinned[kGraphCopies] = {nullptr, nullptr};
+    char *dev_table[kGraphCopies] = {nullptr, nullptr};
+    hipGraphExec_t exec[kGraphCopies] = {nullptr, nullptr};
+    hipEvent_t done[kGraphCopies] = {nullptr, nullptr};
+    bool used[kGraphCopies] = {false, false};
+    int next = 0;
+    bool captured = false;
+    bool autotune = false;
+    bool tuned = false;
+    int precision = MPNL_PREC_FP32;
+    hipStream_t cap = nullptr;
+};
+
+namespace {
+
+// Fill table copy b for the given job pointers (pointers of the shapes are
+// ignored).
+void plan_fill(mpnl_batch *p, int b, const mpnl_job *jobs)
+{
+    char *host = (char *)p->pinned[b];
+    for (const PlanLaunch &L : p->launches) {
+        if (L.kind == L_PATHS) {
+            mpnl::JobDev *jd = (mpnl::JobDev *)(host + L.off);
+            int acc = 0;
+            for (size_t u = 0; u < L.jobs.size(); ++u) {
+                const int i = L.jobs[u];
+                const mpnl::SlotDev &sd = p->sd[i];
+                mpnl::JobDev &J = jd[u];
+                J.yt = p->yt[i];
+                J.rlat = sd.rlat;
+                J.rq = rq_of(sd, p->precision);
+                J.diag = sd.diag;
+                J.permd = sd.permd;
+                J.P = sd.P;
+                J.order = sd.order;
+                J.out = jobs[i].out;
+                J.S = sd.S;
+                J.T = jobs[i].T;
+                J.N = sd.N;
+                J.K = sd.K;
+                J.NP = sd.NP;
+                J.item_begin = acc;
+                acc += sd.S * jobs[i].T;
+            }
+        } else {
+            mpnl::dev::StageJob *sj = (mpnl::dev::StageJob *)(host + L.off);
+            int acc = 0;
+            for (size_t u = 0; u < L.jobs.size(); ++u) {
+                const int i = L.jobs[u];
+                mpnl::dev::StageJob &J = sj[u];
+                J.H = (const float2 *)jobs[i].H;
+                J.y = (const float2 *)jobs[i].y;
+                J.yt = p->yt[i];
+                J.sd = p->sd[i];
+                J.T = jobs[i].T;
+                J.delta = mpnl::dev::delta_of(jobs[i].mod);
+                J.item_begin = acc;
+                acc += L.kind == L_SQRD ? (p->sd[i].S + 1) / 2 : p->sd[i].S;
+            }
+        }
+    }
+}
+
+// Enqueue the whole pipeline of table copy b on `st`: upload, a1, a2, a3,
+// a4+a5.  With `timed`, every launch is bracketed by the context's stage timers.
+hipError_t plan_enqueue(mpnl_batch *p, int b, hipStream_t st, mpnl_ctx *timed = nullptr)
+{
+    hipError_t e = hipMemcpyAsync(p->dev_table[b], p->pinned[b], p->table_bytes, hipMemcpyHostToDevice, st);
+    static const int stage_of[] = {MPNL_STAGE_SQRD, MPNL_STAGE_POSVEC, MPNL_STAGE_ROTATE, MPNL_STAGE_PATHS};
+    for (const PlanLaunch &L : p->launches) {
+        if (e != hipSuccess)
+            break;
+        char *tab = p->dev_table[b] + L.off;
+        const int nj = (int)L.jobs.size();
+        mpnl_ctx off{};
+        StageTimer tm(timed ? timed : &off, stage_of[L.kind], st);
+        switch (L.kind) {
+        case L_SQRD:
+            e = mpnl::launch_sqrd_batch((const mpnl::dev::StageJob *)tab, nj, L.items, L.param, st);
+            break;
+        case L_POSVEC:
+            e = mpnl::launch_posvec_batch((const mpnl::dev::StageJob *)tab, nj, L.items, L.param, L.nmax, st);
+            break;
+        case L_ROTATE:
+            e = mpnl::launch_rotate_batch((const mpnl::dev::StageJob *)tab, nj, L.items, st);
+            break;
+        default:
+            e = mpnl::launch_path_search_multi((const mpnl::JobDev *)tab, nj, L.items, L.param, L.bits, p->precision,
+                                               L.threads, L.chunk, L.grid, st);
+        }
+    }
+    return e;
+}
+
+// Launch shapes tried for a path-search launch of `items` work items:
+// (chunk, grid) with one chunk per workgroup, and persistent grids of 2, 4,
+// 8 and 16 workgroups per compute unit.
+std::vector<std::pair<int, int>> shape_candidates(int items)
+{
+    std::vector<std::pair<int, int>> c;
+    for (int chunk : {1, 2, 4})
+        c.push_back({chunk, (items + chunk - 1) / chunk});
+    for (int chunk : {1, 2})
+        for (int per_cu : {2, 4, 8, 16}) {
+            const int grid = 256 * per_cu;
+            if ((long long)grid * chunk < items)
+                c.push_back({chunk, grid});
+        }
+    return c;
+}
+
+// Time every candidate shape of every path-search launch on the first run's
+// data and keep the fastest (ties: the earlier candidate).
+hipError_t plan_autotune(mpnl_batch *p, const mpnl_job *jobs, hipStream_t st)
+{
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&t1);
+    if (e == hipSuccess) {
+        plan_fill(p, 0, jobs);
+        e = plan_enqueue(p, 0, st);  // produces yt, R and P of every job
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    for (PlanLaunch &L : p->launches) {
+        if (L.kind != L_PATHS || e != hipSuccess)
+            continue;
+        const mpnl::JobDev *tab = (const mpnl::JobDev *)(p->dev_table[0] + L.off);
+        const int nj = (int)L.jobs.size();
+        float best = 1e30f;
+        for (const auto &cand : shape_candidates(L.items)) {
+            float ms = 0.f;
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first pass warms up
+                e = hipEventRecord(t0, st);
+                if (e == hipSuccess)
+                    e = mpnl::launch_path_search_multi(tab, nj, L.items, L.param, L.bits, p->precision, L.threads,
+                                                       cand.first, cand.second, st);
+                if (e == hipSuccess)
+                    e = hipEventRecord(t1, st);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(t1);
+                if (e == hipSuccess)
+                    e = hipEventElapsedTime(&ms, t0, t1);
+            }
+            if (e == hipSuccess && ms < best) {
+                best = ms;
+                L.chunk = cand.first;
+                L.grid = cand.second;
+            }
+        }
+    }
+    if (t0)
+        (void)hipEventDestroy(t0);
+    if (t1)
+        (void)hipEventDestroy(t1);
+    return e;
+}
+
+hipError_t plan_capture(mpnl_batch *p)
+{
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < kGraphCopies && e == hipSuccess; ++b) {
+        hipGraph_t g = nullptr;
+        e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess)
+            break;
+        hipError_t e2 = plan_enqueue(p, b, p->cap);
+        e = hipStreamEndCapture(p->cap, &g);
+        if (e2 != hipSuccess)
+            e = e2;
+        if (e == hipSuccess)
+            e = hipGraphInstantiate(&p->exec[b], g, nullptr, nullptr, 0);
+        if (g)
+            (void)hipGraphDestroy(g);
+    }
+    if (e == hipSuccess)
+        p->captured = true;
+    return e;
+}
+
+bool same_shape(const mpnl_job &a, const mpnl_job &b)
+{
+    return a.S == b.S && a.T == b.T && a.M == b.M && a.N == b.N && a.mod == b.mod && a.n_paths == b.n_paths;
+}
+
+void plan_free(mpnl_ctx *ctx, mpnl_batch *p)
+{
+    for (int b = 0; b < kGraphCopies; ++b) {
+        if (p->done[b])
+            (void)hipEventSynchronize(p->done[b]);
+        if (p->exec[b])
+            (void)hipGraphExecDestroy(p->exec[b]);
+        if (p->done[b])
+            (void)hipEventDestroy(p->done[b]);
+        if (p->pinned[b])
+            (void)hipHostFree(p->pinned[b]);
+    }
+    if (p->cap)
+        (void)hipStreamDestroy(p->cap);
+    if (p->block >= 0)
+        pool_release(ctx, p->block, nullptr);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigned flags, mpnl_batch **out)
+{
+    if (!ctx || !shapes || n_jobs <= 0 || !out || (flags & ~MPNL_BATCH_AUTOTUNE))
+        return MPNL_E_INVAL;
+    *out = nullptr;
+    for (int i = 0; i < n_jobs; ++i) {
+        const mpnl_job &j = shapes[i];
+        if (j.T <= 0)
+            return MPNL_E_INVAL;
+        int rc = validate_shape(j.S, j.M, j.N, j.mod, j.n_paths);
+        if (rc != MPNL_OK)
+            return rc;
+        if (std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N)) > 256)
+            return MPNL_E_UNSUPPORTED;
+        if ((long long)j.S * j.T > INT_MAX / 4)
+            return MPNL_E_UNSUPPORTED;
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok())
+        return hip_fail(ctx, hipErrorInvalidDevice);
+    mpnl_batch *p = new (std::nothrow) mpnl_batch();
+    if (!p)
+        return MPNL_E_NOMEM;
+    p->shapes.assign(shapes, shapes + n_jobs);
+    p->autotune = (flags & MPNL_BATCH_AUTOTUNE) != 0;
+    p->precision = ctx->precision;
+
+    // device memory: every job's slot state and rotated vectors
+    std::vector<SlotLayout> lay(n_jobs);
+    std::vector<size_t> base(n_jobs), ytoff(n_jobs);
+    size_t total = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        const mpnl_job &j = shapes[i];
+        const int K = (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
+        lay[i] = slot_layout(j.S, j.M, j.N, K, (j.N + 3) / 4 * 4, false);
+        base[i] = total;
+        total += lay[i].total;
+        ytoff[i] = total;
+        total += align_up((size_t)j.T * j.S * j.N * sizeof(float2));
+    }
+    // launch groups
+    auto group = [&](int kind, int param, int bits, int threads) -> PlanLaunch & {
+        for (PlanLaunch &L : p->launches)
+            if (L.kind == kind && L.param == param && L.bits == bits && L.threads == threads)
+                return L;
+        PlanLaunch L{};
+        L.kind = kind;
+        L.param = param;
+        L.bits = bits;
+        L.threads = threads;
+        L.chunk = 1;
+        p->launches.push_back(L);
+        return p->launches.back();
+    };
+    for (int stage = 0; stage < 4; ++stage)
+        for (int i = 0; i < n_jobs; ++i) {
+            const mpnl_job &j = shapes[i];
+            const int K = (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
+            PlanLaunch *L;
+            if (stage == L_SQRD) {
+                L = &group(L_SQRD, (j.M + 3) / 4 * 4, 0, 64);
+                L->items += (j.S + 1) / 2;
+            } else if (stage == L_POSVEC) {
+                L = &group(L_POSVEC, K <= 64 ? 1 : K <= 128 ? 2 : 4, 0, 64);
+                L->items += j.S;
+                L->nmax = std::max(L->nmax, j.N);
+            } else if (stage == L_ROTATE) {
+                L = &group(L_ROTATE, 0, 0, 64);
+                L->items += j.S;
+            } else {
+                L = &group(L_PATHS, j.N, j.mod, (K + 63) / 64 * 64);
+                L->items += j.S * j.T;
+                L->grid = L->items;
+            }
+            L->jobs.push_back(i);
+        }
+    p->table_bytes = 0;
+    for (PlanLaunch &L : p->launches) {
+        L.off = p->table_bytes;
+        const size_t entry = L.kind == L_PATHS ? sizeof(mpnl::JobDev) : sizeof(mpnl::dev::StageJob);
+        p->table_bytes += align_up(L.jobs.size() * entry);
+    }
+    ytoff.push_back(0);
+    const size_t tables_at = total;
+    total += kGraphCopies * p->table_bytes;
+
+    int rc = pool_alloc(ctx, total, nullptr, &p->block);
+    if (rc != MPNL_OK) {
+        delete p;
+        return rc;
+    }
+    char *dbase = (char *)ctx->blocks[p->block].ptr;
+    for (int i = 0; i < n_jobs; ++i) {
+        const mpnl_job &j = shapes[i];
+        const SlotLayout &L = lay[i];
+        char *b = dbase + base[i];
+        mpnl::SlotDev sd{};
+        sd.S = j.S;
+        sd.M = j.M;
+        sd.N = j.N;
+        sd.bits = j.mod;
+        sd.K = (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
+        sd.NP = (j.N + 3) / 4 * 4;
+        sd.Qd = (float2 *)(b + L.Qd);
+        sd.roff = (float2 *)(b + L.roff);
+        sd.rlat = (float2 *)(b + L.rlat);
+        sd.rlat_h = (uint32_t *)(b + L.rlat_h);
+        sd.rlat_b = (uint32_t *)(b + L.rlat_b);
+        sd.diag = (float4 *)(b + L.diag);
+        sd.wd = (double *)(b + L.wd);
+        sd.permd = (int32_t *)(b + L.permd);
+        sd.P = (uint8_t *)(b + L.P);
+        sd.order = (uint16_t *)(b + L.order);
+        sd.rec = nullptr;
+        p->sd.push_back(sd);
+        p->yt.push_back((float2 *)(dbase + ytoff[i]));
+    }
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < kGraphCopies && e == hipSuccess; ++b) {
+        p->dev_table[b] = dbase + tables_at + b * p->table_bytes;
+        e = hipHostMalloc(&p->pinned[b], p->table_bytes, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&p->done[b], hipEventDisableTiming);
+    }
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        plan_free(ctx, p);
+        return hip_fail(ctx, e);
+    }
+    ctx->batches.push_back(p);
+    *out = p;
+    return MPNL_OK;
+}
+
+int mpnl_batch_run(mpnl_ctx *ctx, mpnl_batch *p, const mpnl_job *jobs, void *stream)
+{
+    if (!ctx || !p || !jobs || std::find(ctx->batches.begin(), ctx->batches.end(), p) == ctx->batches.end())
+        return MPNL_E_INVAL;
+    for (size_t i = 0; i < p->shapes.size(); ++i)
+        if (!jobs[i].H || !jobs[i].y || !jobs[i].out || !same_shape(jobs[i], p->shapes[i]))
+            return MPNL_E_INVAL;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (!p->tuned) {
+        if (p->autotune)
+            e = plan_autotune(p, jobs, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e);
+        p->tuned = true;
+    }
+    // With stage profiling on, the pipeline is enqueued launch by launch so
+    // that every stage is timed; otherwise the captured graph is replayed.
+    if (!ctx->prof && !p->captured) {
+        e = plan_capture(p);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e);
+    }
+    const int b = p->next;
+    if (p->used[b])
+        e = hipEventSynchronize(p->done[b]);  // its previous run has read the table
+    if (e == hipSuccess) {
+        plan_fill(p, b, jobs);
+        e = ctx->prof ? plan_enqueue(p, b, st, ctx) : hipGraphLaunch(p->exec[b], st);
+    }
+    if (e == hipSuccess)
+        e = hipEventRecord(p->done[b], st);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e);
+    p->used[b] = true;
+    p->next = (b + 1) % kGraphCopies;
+    return MPNL_OK;
+}
+
+int mpnl_batch_info(const mpnl_batch *p, int *n_launches, int *shapes, int max)
+{
+    if (!p || max < 0)
+        return MPNL_E_INVAL;
+    int n = 0;
+    for (const PlanLaunch &L : p->launches)
+        if (L.kind == L_PATHS) {
+            if (shapes && n < max) {
+                int *o = shapes + 5 * n;
+                o[0] = L.param;
+                o[1] = L.bits;
+                o[2] = L.threads;
+                o[3] = L.chunk;
+                o[4] = L.grid;
+            }
+            ++n;
+        }
+    if (n_launches)
+        *n_launches = n;
+    return MPNL_OK;
+}
+
+int mpnl_batch_destroy(mpnl_ctx *ctx, mpnl_batch *p)
+{
+    if (!p)
+        return MPNL_OK;
+    if (!ctx)
+        return MPNL_E_INVAL;
+    auto it = std::find(ctx->batches.begin(), ctx->batches.end(), p);
+    if (it == ctx->batches.end())
+        return MPNL_E_INVAL;
+    ctx->batches.erase(it);
+    DeviceGuard g(ctx->device);
+    plan_free(ctx, p);
+    return MPNL_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,185 @@
+"""Planned multi-cell batches (fixed shapes, graph replay) on the GPU.
+
+A planned batch must give, on every replay, exactly what detecting each job
+alone gives, and the oracle's result on sampled vectors.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity_util import classify
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import paper_2409_14355_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mp):
+    c = mp.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+SMALL = [  # S, T, M, N, bits, paths
+    (120, 14, 8, 6, 2, 64), (75, 14, 16, 16, 4, 128), (40, 14, 32, 20, 6, 256),
+    (33, 3, 5, 5, 4, 256), (64, 14, 12, 12, 4, 64), (17, 1, 32, 32, 4, 200),
+    (90, 7, 4, 4, 2, 16), (50, 14, 24, 9, 6, 100),
+]
+
+
+def _jobs(shapes, seed):
+    jobs, slots = [], []
+    for i, (S, T, M, N, bits, K) in enumerate(shapes):
+        sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=16, seed=(seed, i))
+        slots.append(sl)
+        jobs.append(dict(H=_dev(sl.H), y=_dev(sl.y), mod=bits, n_paths=K,
+                         out=torch.full((T, S, N), -1, dtype=torch.int32, device="cuda:0")))
+    return jobs, slots
+
+
+@pytest.mark.parametrize("autotune", [False, True])
+def test_plan_replays_equal_alone(ctx, autotune):
+    _say("batch plan replays, autotune", autotune)
+    plan = ctx.batch_plan([dict(S=S, T=T, M=M, N=N, mod=b, n_paths=K) for S, T, M, N, b, K in SMALL],
+                          autotune=autotune)
+    try:
+        for rep in range(3):
+            jobs, slots = _jobs(SMALL, 300 + rep)
+            plan.run(jobs)
+            torch.cuda.synchronize()
+            # eager work between replays
+            for j in jobs:
+                alone = ctx.detect(j["H"], j["y"], j["mod"], j["n_paths"])
+                torch.cuda.synchronize()
+                assert torch.equal(alone, j["out"]), (rep, j["H"].shape)
+        shapes = plan.launch_shapes()
+        assert len(shapes) == len({(N, b, (min(K, (1 << b) ** N) + 63) // 64)
+                                   for S, T, M, N, b, K in SMALL})
+        assert all(x["grid"] >= 1 and x["chunk"] >= 1 for x in shapes)
+        # oracle parity on one job of the last replay
+        sl, got = slots[1], jobs[1]["out"].cpu().numpy()
+        ref, diag = oracle.detect_slot("mpnl", sl.H, sl.y, sl.bits, n_paths=SMALL[1][5],
+                                       want_diag=True, nthreads=8)
+        n_bad, counts, unexplained = classify(sl.H, sl.y, got, ref, diag, sl.bits)
+        assert not unexplained, unexplained[:3]
+    finally:
+        plan.close()
+
+
+def test_plan_two_in_flight_and_rebind(ctx):
+    """Back-to-back runs without a host wait use both table copies; each run
+    writes only its own outputs."""
+    _say("batch plan back-to-back")
+    shapes = SMALL[:4]
+    plan = ctx.batch_plan([dict(S=S, T=T, M=M, N=N, mod=b, n_paths=K) for S, T, M, N, b, K in shapes])
+    try:
+        runs = [_jobs(shapes, 320 + r)[0] for r in range(4)]
+        for jobs in runs:
+            plan.run(jobs)
+        torch.cuda.synchronize()
+        for jobs in runs:
+            for j in jobs:
+                alone = ctx.detect(j["H"], j["y"], j["mod"], j["n_paths"])
+                torch.cuda.synchronize()
+                assert torch.equal(alone, j["out"])
+    finally:
+        plan.close()
+
+
+def test_plan_errors(ctx, mp):
+    _say("batch plan errors")
+    shapes = [dict(S=8, T=2, M=4, N=4, mod=2, n_paths=16)]
+    with pytest.raises(mp.MpnlError) as ei:
+        ctx.batch_plan([dict(S=8, T=2, M=8, N=8, mod=4, n_paths=1000)])
+    assert ei.value.code == mp.MPNL_E_UNSUPPORTED
+    with pytest.raises(mp.MpnlError) as ei:
+        ctx.batch_plan([dict(S=8, T=0, M=4, N=4, mod=2, n_paths=16)])
+    assert ei.value.code == mp.MPNL_E_INVAL
+    plan = ctx.batch_plan(shapes)
+    jobs, _ = _jobs([(8, 2, 4, 4, 2, 16)], 330)
+    bad = [dict(jobs[0])]
+    bad[0]["y"] = torch.zeros((3, 8, 4), dtype=torch.complex64, device="cuda:0")  # T differs
+    with pytest.raises(mp.MpnlError) as ei:
+        plan.run(bad)
+    assert ei.value.code == mp.MPNL_E_INVAL
+    plan.run(jobs)
+    torch.cuda.synchronize()
+    h = plan.handle
+    plan.close()
+    assert mp.lib().mpnl_batch_destroy(ctx.handle, h) == mp.MPNL_E_INVAL  # no longer owned
+
+
+def test_plan_forty_cells_full_size(ctx):
+    """Forty uneven cells at full slot sizes: every job equals its alone run,
+    sampled subcarriers of three jobs match the oracle."""
+    cells = synth.draw_cells(40, seed=(340,))
+    shapes = [(c.S, 14, c.M, c.N, c.bits, c.n_paths) for c in cells]
+    _say("forty cells", shapes[:3], "...")
+    plan = ctx.batch_plan([dict(S=S, T=T, M=M, N=N, mod=b, n_paths=K) for S, T, M, N, b, K in shapes],
+                          autotune=True)
+    try:
+        jobs, slots = _jobs(shapes, 341)
+        plan.run(jobs)
+        torch.cuda.synchronize()
+        for j in jobs:
+            alone = ctx.detect(j["H"], j["y"], j["mod"], j["n_paths"])
+            torch.cuda.synchronize()
+            assert torch.equal(alone, j["out"])
+        rng = np.random.default_rng(342)
+        for i in (0, 17, 39):
+            sl, K = slots[i], shapes[i][5]
+            sub = np.sort(rng.choice(sl.H.shape[0], size=24, replace=False))
+            ss = synth.Slot(H=sl.H[sub], y=np.ascontiguousarray(sl.y[:, sub]), s_idx=sl.s_idx[:, sub],
+                            sigma2=sl.sigma2, bits=sl.bits)
+            got = jobs[i]["out"].cpu().numpy()[:, sub]
+            ref, diag = oracle.detect_slot("mpnl", ss.H, ss.y, ss.bits, n_paths=K, want_diag=True,
+                                           nthreads=8)
+            n_bad, counts, unexplained = classify(ss.H, ss.y, got, ref, diag, ss.bits)
+            assert not unexplained, (i, unexplained[:3])
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_plan_reduced_precision_equals_alone(ctx, prec):
+    """A plan made under FP16 / BF16 path metrics gives what detect gives
+    alone under the same precision."""
+    _say("batch plan precision", prec)
+    shapes = SMALL[:5]
+    ctx.set_precision(prec)
+    try:
+        plan = ctx.batch_plan([dict(S=S, T=T, M=M, N=N, mod=b, n_paths=K) for S, T, M, N, b, K in shapes],
+                              autotune=True)
+        try:
+            jobs, _ = _jobs(shapes, 350 + prec)
+            plan.run(jobs)
+            torch.cuda.synchronize()
+            for j in jobs:
+                alone = ctx.detect(j["H"], j["y"], j["mod"], j["n_paths"])
+                torch.cuda.synchronize()
+                assert torch.equal(alone, j["out"])
+            outs = ctx.detect_batch([dict(H=j["H"], y=j["y"], mod=j["mod"], n_paths=j["n_paths"], out=None)
+                                     for j in jobs])
+            torch.cuda.synchronize()
+            for j, o in zip(jobs, outs):
+                assert torch.equal(o, j["out"])
+        finally:
+            plan.close()
+    finally:
+        ctx.set_precision(0)
