@@ -180,7 +180,6 @@ def run_cells(args) -> int:
     import numpy as np
     import torch
 
-    import oracle
     import paper_2409_14355_amd as mp
     import synth
 
@@ -262,7 +261,7 @@ def run_cells(args) -> int:
         "plain_fp32_per_cell_vectors_per_s": plain,
         "speedup_vs_plain": value / plain,
         "ber": ber,
-        "path_launch_shapes": [[x["N"], x["mod"], x["threads"], x["chunk"], x["grid"]]
+        "path_launch_shapes": [[x["N"], x["mod"], x["lanes"], x["vectors_per_workgroup"]]
                                for x in plan.launch_shapes()],
         "stage_ms_per_step": stages,
         "roofline": {"bound": "alu", "kernel": "path_search_batch_kernel", "achieved": achieved,
@@ -271,6 +270,7 @@ def run_cells(args) -> int:
                      "path_ms_per_step": paths_ms / n_prof, "path_launches_per_step": paths_n / n_prof},
     }
     if not args.no_cpu_baseline:
+        import oracle
         n_sub = args.cpu_subcarriers or 24
         cores = os.cpu_count() or 1
         t0 = time.perf_counter()

@@ -215,10 +215,10 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs,
 typedef struct mpnl_batch mpnl_batch;
 
 /* flags of mpnl_batch_create */
-#define MPNL_BATCH_AUTOTUNE 1u  /* on the first run, time candidate launch
-                                   shapes (items per workgroup step, grid
-                                   size) of every path-search launch and keep
-                                   the fastest before capturing              */
+#define MPNL_BATCH_AUTOTUNE 1u  /* on the first run, time the candidate
+                                   shapes (1, 2 or 4 received vectors per
+                                   workgroup) of every path-search launch and
+                                   keep the fastest before capturing         */
 
 /* Plan an uneven multi-cell batch whose job shapes (S, T, M, N, mod, n_paths;
    the pointers are ignored) stay fixed across runs.  Allocates every job's
@@ -245,10 +245,9 @@ int mpnl_batch_run(mpnl_ctx *ctx, mpnl_batch *batch, const mpnl_job *jobs,
 
 /* Launch shapes of the batch's path-search launches: n_launches receives
    their number; shapes (room for max launches, 5 ints each) receives per
-   launch {N, mod, workgroup size, chunk, grid}: the launch's workgroups take
-   `chunk` consecutive (job, subcarrier, symbol) items per step, strided by
-   grid * chunk (a persistent grid when grid * chunk is below the items).
-   Errors: MPNL_E_INVAL for a null batch or negative max. */
+   launch {N, mod, lanes per received vector, received vectors per
+   workgroup, workgroups}.  Errors: MPNL_E_INVAL for a null batch or a
+   negative max. */
 int mpnl_batch_info(const mpnl_batch *batch, int *n_launches, int *shapes,
                     int max);
 

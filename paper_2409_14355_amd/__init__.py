@@ -234,7 +234,7 @@ def mpnl_batch_info(batch: int, max_launches: int = 128) -> list[dict]:
     n = ctypes.c_int()
     v = (ctypes.c_int * (5 * max_launches))()
     _check(lib().mpnl_batch_info(batch, ctypes.byref(n), v, max_launches), "mpnl_batch_info")
-    keys = ("N", "mod", "threads", "chunk", "grid")
+    keys = ("N", "mod", "lanes", "vectors_per_workgroup", "workgroups")
     return [dict(zip(keys, v[5 * i:5 * i + 5])) for i in range(min(n.value, max_launches))]
 
 

@@ -19,10 +19,14 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmpnl.so")
 
 ARCH = "gfx950"
-# Packed fp32 instructions are kept out of all device code.
+# Packed fp32 instructions are kept out of all device code.  The depth loop
+# of the path search must unroll completely at every user count (its
+# residuals then live in registers, not in scratch memory), which needs a
+# higher size limit for explicitly unrolled loops than the default.
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-pragma-unroll-threshold=1000000",
     "-Wno-pass-failed", f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 

@@ -39,6 +39,85 @@ __device__ __forceinline__ cptr<uint32_t> uniform_ptr(const uint32_t *p) { retur
 
 __device__ __forceinline__ float2 ld2(cptr<float> p, int i) { return make_float2(p[2 * i], p[2 * i + 1]); }
 
+// ---------------------------------------------------------------------------
+// Lane exchanges inside a 64-lane wavefront done by the VALU (DPP row
+// operations and gfx950's row swaps), with no trip through the LDS crossbar:
+// lane_xor<S>(x) returns x of lane (lane ^ S).  The block size must be a
+// multiple of 64 (the lane is the low six bits of threadIdx.x).
+// ---------------------------------------------------------------------------
+template <int S>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x)
+{
+    const int v = (int)x;
+    if constexpr (S == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+    } else if constexpr (S == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+    } else if constexpr (S == 4) {
+        const uint32_t from_up = (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x104, 0xF, 0xF, true);  // row_shl:4
+        const uint32_t from_dn = (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x114, 0xF, 0xF, true);  // row_shr:4
+        return (threadIdx.x & 4u) ? from_dn : from_up;
+    } else if constexpr (S == 8) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);  // row_ror:8
+    } else if constexpr (S == 16) {
+        const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        return (threadIdx.x & 16u) ? p[0] : p[1];
+    } else {
+        static_assert(S == 32, "lane distance must be a power of two up to 32");
+        const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        return (threadIdx.x & 32u) ? p[0] : p[1];
+    }
+}
+
+// Run-time distance (constant after unrolling at every call site).
+__device__ __forceinline__ uint32_t lane_xor_n(uint32_t x, int s)
+{
+    switch (s) {
+    case 1: return lane_xor<1>(x);
+    case 2: return lane_xor<2>(x);
+    case 4: return lane_xor<4>(x);
+    case 8: return lane_xor<8>(x);
+    case 16: return lane_xor<16>(x);
+    default: return lane_xor<32>(x);
+    }
+}
+__device__ __forceinline__ int lane_xor_n(int x, int s) { return (int)lane_xor_n((uint32_t)x, s); }
+__device__ __forceinline__ float lane_xor_n(float x, int s)
+{
+    return __uint_as_float(lane_xor_n(__float_as_uint(x), s));
+}
+__device__ __forceinline__ double lane_xor_n(double x, int s)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint64_t lo = lane_xor_n((uint32_t)u, s), hi = lane_xor_n((uint32_t)(u >> 32), s);
+    return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+
+// x of lane l (l uniform across the wave).
+__device__ __forceinline__ uint32_t lane_read(uint32_t x, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
+}
+__device__ __forceinline__ double lane_read(double x, int l)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint64_t lo = lane_read((uint32_t)u, l), hi = lane_read((uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+
+// x of lane 63 - lane: mirror inside each row of 16, then swap the rows.
+__device__ __forceinline__ uint32_t lane_mirror(uint32_t x)
+{
+    const uint32_t m = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, true);  // row_mirror
+    return lane_xor<32>(lane_xor<16>(m));
+}
+__device__ __forceinline__ double lane_mirror(double x)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint64_t lo = lane_mirror((uint32_t)u), hi = lane_mirror((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+
 __device__ __forceinline__ int gray_code(int m) { return m ^ (m >> 1); }
 __device__ __forceinline__ int gray_decode(int g) { return g ^ (g >> 1) ^ (g >> 2); }
 
@@ -119,7 +198,7 @@ __device__ __forceinline__ void axis_second(float z, float m0, float lv0, float 
 {
     const float s = (z >= lv0) ? 1.f : -1.f;
     const float a = m0 + s;
-    m1 = (a >= 0.f && a <= (float)(L - 1)) ? a : m0 - s;
+    m1 = ((a >= 0.f) & (a <= (float)(L - 1))) ? a : m0 - s;
     const float d1 = z - level_of<L>(m1);
     e1 = d1 * d1;
 }
@@ -163,8 +242,8 @@ __device__ __forceinline__ void kth_small(float zI, float zQ, int k, float &mI, 
     const float c10 = ei[0] + e0Q, c01 = e0I + eq[0];
     const float c20 = ei[1] + e0Q, c02 = e0I + eq[1];
     const bool firstI = c10 <= c01;
-    const bool third20 = firstI && c20 <= c01;   // ranks 2, 3 = (1,0), (2,0)
-    const bool third02 = !firstI && c02 < c10;   // ranks 2, 3 = (0,1), (0,2)
+    const bool third20 = firstI & (c20 <= c01);   // ranks 2, 3 = (1,0), (2,0)
+    const bool third02 = !firstI & (c02 < c10);   // ranks 2, 3 = (0,1), (0,2)
     int ci, cj;
     if (k == 3) {
         ci = firstI ? (third20 ? 2 : 0) : (third02 ? 0 : 1);
@@ -179,8 +258,8 @@ __device__ __forceinline__ void kth_small(float zI, float zQ, int k, float &mI, 
         cj = a ? 0 : 3;
     } else {
         const float c11 = ei[0] + eq[0];         // (2,0), (1,1) or (0,2)
-        const bool a = c20 <= c11 && c20 <= c02;
-        const bool b = !a && c11 <= c02;
+        const bool a = (c20 <= c11) & (c20 <= c02);
+        const bool b = !a & (c11 <= c02);
         ci = a ? 2 : b ? 1 : 0;
         cj = a ? 0 : b ? 1 : 2;
     }
@@ -190,86 +269,59 @@ __device__ __forceinline__ void kth_small(float zI, float zQ, int k, float &mI, 
     eQ = cj == 0 ? e0Q : cj == 1 ? eq[0] : cj == 2 ? eq[1] : eq[2];
 }
 
-// Exact k-th closest point for any k (used for k > 4): merge of L sorted
-// rows, one per in-phase level, over the quadrature levels sorted by
-// distance; every row's next candidate is kept, the smallest is taken k
-// times.  Equal costs resolve to the lower in-phase level.
+// Exact k-th closest point for k > 4, computed by the whole wavefront.  The
+// lanes that need it at this depth are served in rounds: a round takes the
+// received value z of one of them, lane c evaluates constellation point
+// c mod L^2 against z, the wave sorts the points by (cost, constellation
+// index) with a bitonic network over L^2 lanes, and every needing lane whose
+// value equals z reads entry k-1 of the sorted list.  Lanes that share a
+// path prefix share z, so one round usually serves all of them.  Must be
+// reached by every lane of the wave.
 template <int L>
-__device__ __forceinline__ void kth_lattice(float zI, float zQ, int k, float &mI, float &mQ, float &eIo,
-                                            float &eQo)
+__device__ __forceinline__ void kth_wave(bool need, float zI, float zQ, int k, float &mI, float &mQ, float &eI,
+                                         float &eQ)
 {
-    // quadrature levels sorted by distance: two-pointer walk from the closest
-    float mq0;
-    nearest_level<L>(zQ, mq0);
-    int ordQ[L];
-    float eQ[L];
-    {
-        const int q0 = (int)mq0;
-        ordQ[0] = q0;
-        const float dd = zQ - level_of<L>((float)q0);
-        eQ[0] = dd * dd;
-        int lo = q0 - 1, hi = q0 + 1;
+    constexpr int HB = Axis<L>::HB;
+    constexpr int NPT = L * L;  // 16 or 64 points: sorted within rows of NPT lanes
+    const int lane = (int)(threadIdx.x & 63u);
+    const int c = lane & (NPT - 1);
+    const int cI = c & (L - 1), cQ = c >> HB;
+    const int cidx = (gray_code(cI) << HB) | gray_code(cQ);
+    const float vI = level_of<L>((float)cI), vQ = level_of<L>((float)cQ);
+    uint64_t pend = __ballot(need);
+    while (pend) {
+        const int src = __builtin_ctzll(pend);
+        const float zi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zI), src));
+        const float zq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zQ), src));
+        const float dI = zi - vI, dQ = zq - vQ;
+        float key = dI * dI + dQ * dQ;
+        int kid = cidx;
 #pragma unroll
-        for (int t = 1; t < L; ++t) {
-            const float dl = zQ - level_of<L>((float)lo), dh = zQ - level_of<L>((float)hi);
-            const float elo = lo >= 0 ? dl * dl : INFINITY;
-            const float ehi = hi < L ? dh * dh : INFINITY;
-            const bool take_hi = ehi < elo || lo < 0;
-            ordQ[t] = take_hi ? hi : lo;
-            eQ[t] = take_hi ? ehi : elo;
-            hi += take_hi ? 1 : 0;
-            lo -= take_hi ? 0 : 1;
-        }
-    }
-    int ptr[L];
-    float cand[L];
+        for (int size = 2; size <= NPT; size <<= 1) {
 #pragma unroll
-    for (int i = 0; i < L; ++i) {
-        const float dd = zI - level_of<L>((float)i);
-        ptr[i] = 0;
-        cand[i] = dd * dd + eQ[0];
-    }
-    int bi = 0;
-    for (int step = 0;; ++step) {
-        bi = 0;
-        float bc = cand[0];
-#pragma unroll
-        for (int i = 1; i < L; ++i) {
-            const bool lt = cand[i] < bc;
-            bi = lt ? i : bi;
-            bc = lt ? cand[i] : bc;
-        }
-        if (step >= k - 1 || step >= L * L - 1)
-            break;
-#pragma unroll
-        for (int i = 0; i < L; ++i)
-            if (i == bi) {
-                const int p = ptr[i] + 1;
-                float eq = INFINITY;
-#pragma unroll
-                for (int t = 1; t < L; ++t)
-                    eq = (t == p) ? eQ[t] : eq;
-                const float dd = zI - level_of<L>((float)i);
-                ptr[i] = p;
-                cand[i] = dd * dd + eq;
+            for (int j = size >> 1; j > 0; j >>= 1) {
+                const float ok = lane_xor_n(key, j);
+                const int oid = lane_xor_n(kid, j);
+                const bool up = size == NPT || (lane & size) == 0;
+                const bool lower = (lane & j) == 0;
+                const bool other_first = (ok < key) | ((ok == key) & (oid < kid));
+                const bool take = (lower == up) == other_first;
+                key = take ? ok : key;
+                kid = take ? oid : kid;
             }
+        }
+        const bool mine = need && ((zI == zi && zQ == zq) || lane == src);
+        const int from = (lane & ~(NPT - 1)) + min(max(k, 1), NPT) - 1;
+        const int got = __shfl(kid, from);
+        if (mine) {
+            mI = (float)gray_decode(got >> HB);
+            mQ = (float)gray_decode(got & (L - 1));
+            const float eI1 = zI - level_of<L>(mI), eQ1 = zQ - level_of<L>(mQ);
+            eI = eI1 * eI1;
+            eQ = eQ1 * eQ1;
+        }
+        pend &= ~__ballot(mine);
     }
-    int pp = 0;
-#pragma unroll
-    for (int i = 0; i < L; ++i)
-        pp = (i == bi) ? ptr[i] : pp;
-    int mq = ordQ[0];
-    float eq = eQ[0];
-#pragma unroll
-    for (int t = 1; t < L; ++t) {
-        mq = (t == pp) ? ordQ[t] : mq;
-        eq = (t == pp) ? eQ[t] : eq;
-    }
-    const float dI = zI - level_of<L>((float)bi);
-    mI = (float)bi;
-    mQ = (float)mq;
-    eIo = dI * dI;
-    eQo = eq;
 }
 
 // ============================================================================
@@ -343,9 +395,9 @@ __device__ __forceinline__ float descend(cptr<float> yv, cptr<float> dg, cptr<fl
                 }
             } else if (k == 3 || k == 4) {
                 kth_small<L>(zI, zQ, k, mI, lI, eI, mQ, lQ, eQ);
-            } else if (k > 4) {
-                kth_lattice<L>(zI, zQ, k, mI, mQ, eI, eQ);
             }
+            if constexpr (L > 2)
+                kth_wave<L>(k > 4, zI, zQ, k, mI, mQ, eI, eQ);
         }
         metric = fmaf(gw, eI + eQ, metric);
         decf[d >> 2] = fmaf(fmaf(mQ, (float)L, mI), code_weight(d), decf[d >> 2]);
@@ -400,72 +452,83 @@ __device__ __forceinline__ int32_t decision_index(const float *decf, int d)
 
 __device__ __forceinline__ bool better(float m, int r, float bm, int br)
 {
-    return m < bm || (m == bm && r < br);
+    return (m < bm) | ((m == bm) & (r < br));
 }
 
 // Minimum (metric, path) over the workgroup; returns the winning path index.
-__device__ __forceinline__ int block_argmin(float bm, int br, float *sm, int *sr)
+__device__ __forceinline__ int block_argmin(float bm, int br, int W, float *sm, int *sr)
 {
     float wm = bm;
     int wr = br;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        const float om = __shfl_xor(wm, off);
-        const int orr = __shfl_xor(wr, off);
+        const float om = lane_xor_n(wm, off);
+        const int orr = lane_xor_n(wr, off);
         if (better(om, orr, wm, wr)) {
             wm = om;
             wr = orr;
         }
     }
+    if (W == 64)  // one wave per vector: no exchange between waves
+        return wr;
     const int wid = threadIdx.x >> 6;
-    const int nwv = (blockDim.x + 63) >> 6;
+    const int wpv = W >> 6;
+    const int w0 = wid - wid % wpv;
     if ((threadIdx.x & 63) == 0) {
         sm[wid] = wm;
         sr[wid] = wr;
     }
     __syncthreads();
-    float gm = sm[0];
-    int gr = sr[0];
-    for (int w = 1; w < nwv; ++w)
-        if (better(sm[w], sr[w], gm, gr)) {
-            gm = sm[w];
-            gr = sr[w];
+    float gm = sm[w0];
+    int gr = sr[w0];
+    for (int w = 1; w < wpv; ++w)
+        if (better(sm[w0 + w], sr[w0 + w], gm, gr)) {
+            gm = sm[w0 + w];
+            gr = sr[w0 + w];
         }
     return gr;
 }
 
-// One lane runs one path: lane tid of path group g runs path g * blockDim +
-// tid of one received vector.  With one group the winner writes its symbols
-// in user order; with several, each group leaves its best (metric, path,
-// decisions) for path_group_reduce_kernel.
+// The W lanes (whole waves) tid = 0..W-1 given to one received vector run
+// one path each: lane tid of path group g runs path g * W + tid.  With one
+// group the winner writes its symbols in user order; with several, each group
+// leaves its best (metric, path, decisions) for path_group_reduce_kernel.
+// Every lane of the workgroup calls this (it may synchronise the workgroup);
+// lanes of an inactive vector do no work.
 template <int N, int L, int PREC>
 __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cptr<float> rl,
                                               cptr<uint32_t> rq, const uint8_t *Pbase,
                                               const uint16_t *order, int K, int NP, int group,
                                               const int32_t *pm, int32_t *o, float *part, float *sm,
-                                              int *sr)
+                                              int *sr, int W, int tid, bool active)
 {
     constexpr int NW = (N + 3) / 4;
     const uint32_t *Pw = (const uint32_t *)Pbase;
     const int nw = NP >> 2;
-    const int li = group * (int)blockDim.x + (int)threadIdx.x;
+    const int li = group * W + tid;
     float bm = INFINITY;
     int br = INT_MAX;
     float decf[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w)
         decf[w] = 0.f;
-    if (li < K) {
-        const int r = order ? (int)order[li] : li;
+    // Whole waves descend (the k > 4 choice is wave-cooperative); lanes past
+    // the last path follow the first choice everywhere and are discarded.
+    if (active && li - (int)(threadIdx.x & 63u) < K) {
+        const bool valid = li < K;
+        const int r = valid ? (order ? (int)order[li] : li) : 0;
         uint32_t pw[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w)
-            pw[w] = Pw[(size_t)r * nw + w];
-        bm = descend<N, L, PREC>(yv, dg, rl, rq, pw, decf);
-        br = r;
+            pw[w] = valid ? Pw[(size_t)r * nw + w] : 0x01010101u;
+        const float m = descend<N, L, PREC>(yv, dg, rl, rq, pw, decf);
+        if (valid) {
+            bm = m;
+            br = r;
+        }
     }
-    const int gr = block_argmin(bm, br, sm, sr);
-    if (br != gr)
+    const int gr = block_argmin(bm, br, W, sm, sr);
+    if (!active || br != gr)
         return;
     if (part == nullptr) {
 #pragma unroll
@@ -497,7 +560,8 @@ __global__ __launch_bounds__(256) void path_search_kernel(PathArgs a)
     float *part = a.part ? a.part + (v * gridDim.y + blockIdx.y) * (2 + (N + 3) / 4) : nullptr;
     search_vector<N, L, PREC>(uniform_ptr(a.yt + v * N), uniform_ptr(a.diag + sN), uniform_ptr(a.rlat + sN * N),
                               rq, a.P + (size_t)s * a.K * a.NP, a.order ? a.order + (size_t)s * a.K : nullptr,
-                              a.K, a.NP, blockIdx.y, a.permd + sN, a.out + v * N, part, sm, sr);
+                              a.K, a.NP, blockIdx.y, a.permd + sN, a.out + v * N, part, sm, sr, (int)blockDim.x,
+                              (int)threadIdx.x, true);
 }
 
 // Best of the path groups of every received vector (equal metrics: lowest
@@ -546,18 +610,26 @@ __device__ __forceinline__ void soft_vector(const PathArgs &a, int s, int t, uns
     const uint32_t *Pw = (const uint32_t *)(a.P + (size_t)s * K * a.NP);
     float *mets = (float *)smem;          // K
     float *decs = mets + K;               // K * NW
-    for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    // whole waves descend (see search_vector)
+    for (int r0 = 0; r0 < K; r0 += blockDim.x) {
+        const int r = r0 + (int)threadIdx.x;
+        if (r - (int)(threadIdx.x & 63u) >= K)
+            continue;
+        const bool valid = r < K;
         uint32_t pw[NW];
         float decf[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-            pw[w] = Pw[(size_t)r * nw + w];
+            pw[w] = valid ? Pw[(size_t)r * nw + w] : 0x01010101u;
             decf[w] = 0.f;
         }
-        mets[r] = descend<N, L, PREC_FP32>(yv, dg, rl, nullptr, pw, decf);
+        const float m = descend<N, L, PREC_FP32>(yv, dg, rl, nullptr, pw, decf);
+        if (valid) {
+            mets[r] = m;
 #pragma unroll
-        for (int w = 0; w < NW; ++w)
-            decs[(size_t)r * NW + w] = decf[w];
+            for (int w = 0; w < NW; ++w)
+                decs[(size_t)r * NW + w] = decf[w];
+        }
     }
     __syncthreads();
     const int32_t *pm = a.permd + sN;
@@ -627,16 +699,15 @@ __global__ __launch_bounds__(256) void path_search_soft_kernel(PathArgs a)
 
 // ============================================================================
 // Path search over many jobs (cells) that share the user count N and the
-// modulation.  Work items are (job, subcarrier, symbol), numbered job by job;
-// workgroup b takes chunks of `chunk` consecutive items: chunk b, b + grid,
-// b + 2 grid, ... (a persistent, statically strided grid when grid * chunk
-// is below the item count).  Each item is processed exactly as
-// path_search_kernel processes it, so a job's result does not depend on the
-// other jobs of the launch.
+// modulation.  Work items are (job, subcarrier, symbol), numbered job by job.
+// A workgroup holds vpw received vectors of W = blockDim / vpw lanes each:
+// vector slot q of workgroup b runs item b * vpw + q exactly as
+// path_search_kernel runs it, so a job's result does not depend on the other
+// jobs of the launch or on vpw.
 // ============================================================================
 struct MultiArgs {
     const JobDev *jobs;
-    int n_jobs, total_items, chunk;
+    int n_jobs, total_items, vpw;
 };
 
 template <int N, int L, int PREC>
@@ -644,24 +715,20 @@ __global__ __launch_bounds__(256) void path_search_multi_kernel(MultiArgs a)
 {
     __shared__ float sm[4];
     __shared__ int sr[4];
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int stride = gridDim.x * a.chunk;
-    for (int i0 = lb * a.chunk; i0 < a.total_items; i0 += stride) {
-        const int i1 = min(i0 + a.chunk, a.total_items);
-        for (int item = i0; item < i1; ++item) {
-            const JobDev &j = a.jobs[find_job(a.jobs, a.n_jobs, item)];
-            const int li = item - j.item_begin;
-            const int s = li / j.T, t = li - s * j.T;
-            const size_t sN = (size_t)s * N;
-            const size_t v = (size_t)t * j.S + s;
-            cptr<uint32_t> rq = j.rq ? uniform_ptr(j.rq + sN * N) : nullptr;
-            search_vector<N, L, PREC>(uniform_ptr(j.yt + v * N), uniform_ptr(j.diag + sN),
-                                      uniform_ptr(j.rlat + sN * N), rq, j.P + (size_t)s * j.K * j.NP,
-                                      j.order ? j.order + (size_t)s * j.K : nullptr, j.K, j.NP, 0,
-                                      j.permd + sN, j.out + v * N, nullptr, sm, sr);
-            __syncthreads();
-        }
-    }
+    const int W = (int)blockDim.x / a.vpw;
+    const int q = __builtin_amdgcn_readfirstlane((int)threadIdx.x / W);  // whole waves per slot
+    const int item = xcd_remap(blockIdx.x, gridDim.x) * a.vpw + q;
+    const bool active = item < a.total_items;
+    const JobDev &j = a.jobs[find_job(a.jobs, a.n_jobs, active ? item : a.total_items - 1)];
+    const int li = (active ? item : a.total_items - 1) - j.item_begin;
+    const int s = li / j.T, t = li - s * j.T;
+    const size_t sN = (size_t)s * N;
+    const size_t v = (size_t)t * j.S + s;
+    cptr<uint32_t> rq = j.rq ? uniform_ptr(j.rq + sN * N) : nullptr;
+    search_vector<N, L, PREC>(uniform_ptr(j.yt + v * N), uniform_ptr(j.diag + sN), uniform_ptr(j.rlat + sN * N), rq,
+                              j.P + (size_t)s * j.K * j.NP, j.order ? j.order + (size_t)s * j.K : nullptr, j.K,
+                              j.NP, 0, j.permd + sN, j.out + v * N, nullptr, sm, sr, W, (int)threadIdx.x - q * W,
+                              active);
 }
 
 inline float delta_of(int bits)

@@ -228,16 +228,18 @@ hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, f
 }
 
 hipError_t launch_path_search_multi(const JobDev *jobs_dev, int n_jobs, int total_items, int N, int bits,
-                                    int precision, int threads, int chunk, int grid, hipStream_t st)
+                                    int precision, int threads, int vpw, hipStream_t st)
 {
-    if (N < 1 || N > 32 || chunk < 1 || grid < 1 || threads < 64 || threads > 256 || threads % 64)
+    if (N < 1 || N > 32 || threads < 64 || threads % 64 || (vpw != 1 && vpw != 2 && vpw != 4) ||
+        threads * vpw > 256 || total_items < 1)
         return hipErrorInvalidValue;
     MultiArgs a;
     a.jobs = jobs_dev;
     a.n_jobs = n_jobs;
     a.total_items = total_items;
-    a.chunk = chunk;
-    return kMultiLaunch[N - 1](a, bits, precision, threads, grid, st);
+    a.vpw = vpw;
+    const int grid = (total_items + vpw - 1) / vpw;
+    return kMultiLaunch[N - 1](a, bits, precision, threads * vpw, grid, st);
 }
 
 }  // namespace mpnl

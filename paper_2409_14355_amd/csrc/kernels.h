@@ -53,10 +53,11 @@ hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, f
                                    float clip, float *llr, int32_t *out, hipStream_t st);
 // Batched path search over many jobs sharing (NMAX bucket, bits); one persistent launch.
 // Path search of many jobs with the same N and modulation (each with
-// n_paths <= 256; threads = n_paths rounded up to 64), chunk consecutive
-// items per workgroup step, `grid` workgroups.
+// n_paths <= threads, threads a multiple of 64), one work item (job,
+// subcarrier, symbol) per `threads` lanes, vpw in {1, 2, 4} items per
+// workgroup (threads * vpw <= 256).
 hipError_t launch_path_search_multi(const JobDev *jobs_dev, int n_jobs, int total_items, int N, int bits,
-                                    int precision, int threads, int chunk, int grid, hipStream_t st);
+                                    int precision, int threads, int vpw, hipStream_t st);
 
 namespace dev {
 struct StageJob;

@@ -77,9 +77,9 @@ __device__ __forceinline__ void sqrd_body(const SqrdArgs &a, int pair)
         int id = cand ? c : (1 << 20);
 #pragma unroll
         for (int off = 16; off > 0; off >>= 1) {
-            const double ok = __shfl_xor(key, off, 32);
-            const int oid = __shfl_xor(id, off, 32);
-            if (ok < key || (ok == key && oid < id)) {
+            const double ok = lane_xor_n(key, off);  // stays inside the 32-lane half
+            const int oid = lane_xor_n(id, off);
+            if ((ok < key) | ((ok == key) & (oid < id))) {
                 key = ok;
                 id = oid;
             }

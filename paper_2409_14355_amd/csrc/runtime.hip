@@ -748,7 +748,7 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
                 const mpnl::JobDev *jd = (const mpnl::JobDev *)(dev + goff[q]);
                 StageTimer tm(ctx, MPNL_STAGE_PATHS, st);
                 e = mpnl::launch_path_search_multi(jd, (int)groups[q].idx.size(), items[q], groups[q].N,
-                                                   groups[q].bits, ctx->precision, threads[q], 1, items[q], st);
+                                                   groups[q].bits, ctx->precision, threads[q], 1, st);
             }
             if (e != hipSuccess)
                 rc = hip_fail(ctx, e);
@@ -780,8 +780,7 @@ struct PlanLaunch {
     int bits;         // a4
     int threads;      // a4 workgroup size
     int nmax;         // a2: largest N (LDS size)
-    int chunk;        // a4: items per workgroup step (tuned)
-    int grid;         // a4: workgroups (tuned; below items / chunk = persistent)
+    int vpw;          // a4: received vectors per workgroup (tuned)
     int items;
     size_t off;       // byte offset of the job table in a table buffer
     std::vector<int> jobs;
@@ -886,31 +885,15 @@ hipError_t plan_enqueue(mpnl_batch *p, int b, hipStream_t st, mpnl_ctx *timed = 
             break;
         default:
             e = mpnl::launch_path_search_multi((const mpnl::JobDev *)tab, nj, L.items, L.param, L.bits, p->precision,
-                                               L.threads, L.chunk, L.grid, st);
+                                               L.threads, L.vpw, st);
         }
     }
     return e;
 }
 
-// Launch shapes tried for a path-search launch of `items` work items:
-// (chunk, grid) with one chunk per workgroup, and persistent grids of 2, 4,
-// 8 and 16 workgroups per compute unit.
-std::vector<std::pair<int, int>> shape_candidates(int items)
-{
-    std::vector<std::pair<int, int>> c;
-    for (int chunk : {1, 2, 4})
-        c.push_back({chunk, (items + chunk - 1) / chunk});
-    for (int chunk : {1, 2})
-        for (int per_cu : {2, 4, 8, 16}) {
-            const int grid = 256 * per_cu;
-            if ((long long)grid * chunk < items)
-                c.push_back({chunk, grid});
-        }
-    return c;
-}
-
-// Time every candidate shape of every path-search launch on the first run's
-// data and keep the fastest (ties: the earlier candidate).
+// Time every candidate shape (1, 2 or 4 received vectors per workgroup, as
+// the workgroup size allows) of every path-search launch on the first run's
+// data and keep the fastest (ties: fewer vectors per workgroup).
 hipError_t plan_autotune(mpnl_batch *p, const mpnl_job *jobs, hipStream_t st)
 {
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -929,13 +912,15 @@ hipError_t plan_autotune(mpnl_batch *p, const mpnl_job *jobs, hipStream_t st)
         const mpnl::JobDev *tab = (const mpnl::JobDev *)(p->dev_table[0] + L.off);
         const int nj = (int)L.jobs.size();
         float best = 1e30f;
-        for (const auto &cand : shape_candidates(L.items)) {
+        if (2 * L.threads > 256)
+            continue;  // a single candidate
+        for (int vpw = 1; vpw <= 4 && vpw * L.threads <= 256; vpw *= 2) {
             float ms = 0.f;
             for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first pass warms up
                 e = hipEventRecord(t0, st);
                 if (e == hipSuccess)
                     e = mpnl::launch_path_search_multi(tab, nj, L.items, L.param, L.bits, p->precision, L.threads,
-                                                       cand.first, cand.second, st);
+                                                       vpw, st);
                 if (e == hipSuccess)
                     e = hipEventRecord(t1, st);
                 if (e == hipSuccess)
@@ -945,8 +930,7 @@ hipError_t plan_autotune(mpnl_batch *p, const mpnl_job *jobs, hipStream_t st)
             }
             if (e == hipSuccess && ms < best) {
                 best = ms;
-                L.chunk = cand.first;
-                L.grid = cand.second;
+                L.vpw = vpw;
             }
         }
     }
@@ -1057,7 +1041,7 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
         L.param = param;
         L.bits = bits;
         L.threads = threads;
-        L.chunk = 1;
+        L.vpw = 1;
         p->launches.push_back(L);
         return p->launches.back();
     };
@@ -1079,7 +1063,6 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
             } else {
                 L = &group(L_PATHS, j.N, j.mod, (K + 63) / 64 * 64);
                 L->items += j.S * j.T;
-                L->grid = L->items;
             }
             L->jobs.push_back(i);
         }
@@ -1196,8 +1179,8 @@ int mpnl_batch_info(const mpnl_batch *p, int *n_launches, int *shapes, int max)
                 o[0] = L.param;
                 o[1] = L.bits;
                 o[2] = L.threads;
-                o[3] = L.chunk;
-                o[4] = L.grid;
+                o[3] = L.vpw;
+                o[4] = (L.items + L.vpw - 1) / L.vpw;
             }
             ++n;
         }
