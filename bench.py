@@ -36,6 +36,9 @@ DTYPES = {"fp32": "f32", "fp16": "f16-operands/f32-accumulate", "bf16": "bf16-op
 # modulation uniform over QPSK/16-QAM/64-QAM, subcarriers U{300..3276},
 # 14 symbols, i.i.d. Rayleigh, 20 dB, paths from {64, 128, 256}
 CELLS_WORKLOAD = "cells40-U4-32-S300-3276-T14"
+# serving: Poisson arrivals of slot jobs whose shapes follow the 40-cell
+# distribution, Kronecker channel (0.5 / 0.3) at 18 dB, 0.5 ms deadline
+SERVING_WORKLOAD = "serving-poisson20k-cells-kron18"
 
 
 def path_flops_per_vector(N: int, K: int) -> int:
@@ -68,7 +71,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="16x16-qam16-S1200-T14",
-                    choices=sorted(WORKLOADS) + [CELLS_WORKLOAD])
+                    choices=sorted(WORKLOADS) + [CELLS_WORKLOAD, SERVING_WORKLOAD])
+    ap.add_argument("--rate", type=float, default=20000.0, help="serving: offered jobs/s")
+    ap.add_argument("--jobs", type=int, default=2000, help="serving: jobs per run")
     ap.add_argument("--no-autotune", action="store_true", help="batch workload: default grid sizes")
     ap.add_argument("--paths", type=int, default=0)
     ap.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS))
@@ -84,6 +89,8 @@ def main() -> int:
 
     if args.workload == CELLS_WORKLOAD:
         return run_cells(args)
+    if args.workload == SERVING_WORKLOAD:
+        return run_serving(args)
 
     import numpy as np
     import torch
@@ -285,6 +292,111 @@ def run_cells(args) -> int:
                                          f"{len(cells)} cells ({nv} vectors, {dt:.1f} s wall)"}
     plan.close()
     ctx.close()
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def _serving_stats(comp, vec_of, pool_idx=None):
+    import numpy as np
+
+    import paper_2409_14355_amd as mp
+    st = np.array([c["status"] for c in comp])
+    done = [c for c in comp if c["status"] == mp.MPNL_JOB_DONE]
+    lat = np.array([c["done_us"] - c["arrival_us"] for c in done]) if done else np.zeros(1)
+    t0 = min(c["arrival_us"] for c in comp)
+    t1 = max(c["done_us"] for c in comp)
+    vecs = sum(vec_of(c) for c in done)
+    return {"offered": len(comp), "done": int((st == mp.MPNL_JOB_DONE).sum()),
+            "rejected": int((st == mp.MPNL_JOB_REJECTED).sum()),
+            "dropped": int((st == mp.MPNL_JOB_DROPPED).sum()),
+            "failed": int((st == mp.MPNL_JOB_FAILED).sum()),
+            "vectors_per_s": vecs / ((t1 - t0) * 1e-6), "span_ms": (t1 - t0) * 1e-3,
+            "p50_latency_ms": float(np.percentile(lat, 50)) * 1e-3,
+            "p99_latency_ms": float(np.percentile(lat, 99)) * 1e-3,
+            "deadline_met": float((lat <= 500.0).mean()) if done else 0.0}
+
+
+def run_serving(args) -> int:
+    """Poisson arrivals through the continuous-batching server: the offered
+    rate, and a rate the device sustains, in FP32 and in FP16 path metrics."""
+    import numpy as np
+    import torch
+
+    import paper_2409_14355_amd as mp
+    import synth
+
+    T, snr, n_pool = 14, 18.0, 48
+    cells = synth.draw_cells(n_pool, seed=(3, 0))
+    dev = torch.device("cuda:0")
+    pool = []
+    for i, c in enumerate(cells):
+        sl = synth.make_slot(S=c.S, T=T, M=c.M, N=c.N, bits=c.bits, snr_db=snr, seed=(3, 1, i),
+                             channel="kron", rho_rx=0.5, rho_tx=0.3)
+        pool.append(dict(H=torch.from_numpy(sl.H).to(dev), y=torch.from_numpy(sl.y).to(dev), mod=c.bits,
+                         n_paths=c.n_paths, out=torch.empty((T, c.S, c.N), dtype=torch.int32, device=dev)))
+    ctx = mp.Context(0)
+    cfg = mp.server_config(hbm_budget=16 << 30, max_batch_jobs=8, max_inflight=3, max_queue=256,
+                           deadline_us=500.0, drop_late=True)
+    seed = 31
+
+    def run(rate, n_jobs, prec):
+        nonlocal seed
+        ctx.set_precision(prec)
+        srv = mp.Server(ctx, cfg)
+        try:
+            comp = srv.run_poisson(pool, n_jobs, rate, seed)
+        finally:
+            srv.close()
+        seed += 1
+        torch.cuda.synchronize()
+        return comp
+
+    mean_vec = float(np.mean([c.S * T for c in cells]))
+
+    def stats(comp):
+        return _serving_stats(comp, lambda c: cells[c["entry"]].S * T)
+
+    for j in pool:  # warm the allocator and code paths
+        ctx.detect(j["H"], j["y"], j["mod"], j["n_paths"], j["out"])
+    run(2000.0, 50, 0)
+    run(2000.0, 50, 1)
+    # closed-loop capacity: every job queued at once
+    cap_cfg = mp.server_config(max_batch_jobs=8, max_inflight=3)
+    caps = {}
+    for prec in (0, 1):
+        ctx.set_precision(prec)
+        srv = mp.Server(ctx, cap_cfg)
+        try:
+            t0 = srv.now_us()
+            for i, j in enumerate(pool * 4):
+                srv.submit(j, i, t0)
+            comp = srv.drain()
+        finally:
+            srv.close()
+        torch.cuda.synchronize()
+        span = max(c["done_us"] for c in comp) - t0
+        caps[prec] = len(comp) / (span * 1e-6)
+    res_runs = {}
+    for prec, name in ((0, "fp32"), (1, "fp16")):
+        offered = stats(run(args.rate, args.jobs, prec))
+        sus_rate = 0.7 * caps[prec]
+        sustained = stats(run(sus_rate, max(200, int(sus_rate * 0.3)), prec))
+        res_runs[name] = {"capacity_jobs_per_s": caps[prec], "at_offered_rate": offered,
+                          "at_70pct_capacity": dict(sustained, rate_jobs_per_s=sus_rate)}
+    ctx.close()
+    main_run = res_runs["fp16"]["at_offered_rate"]
+    res = {
+        "metric": METRIC, "value": main_run["vectors_per_s"], "unit": "vectors/s", "n_gpus": 1,
+        "steps": args.jobs, "warmup": 50, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPES["fp16"], "data": "synthetic",
+        "config": {"workload": SERVING_WORKLOAD, "offered_jobs_per_s": args.rate, "jobs_per_run": args.jobs,
+                   "pool_jobs": n_pool, "mean_vectors_per_job": mean_vec, "symbols": T, "snr_db": snr,
+                   "channel": "kron 0.5/0.3", "deadline_us": 500.0, "max_batch_jobs": 8, "max_inflight": 3,
+                   "max_queue": 256, "drop_late": True, "hbm_budget_bytes": 16 << 30},
+        "p50_latency_ms": main_run["p50_latency_ms"], "p99_latency_ms": main_run["p99_latency_ms"],
+        "runs": res_runs,
+        "mixed_vs_fp32_capacity": caps[1] / caps[0],
+    }
     print(json.dumps(res), flush=True)
     return 0
 

@@ -254,6 +254,105 @@ int mpnl_batch_info(const mpnl_batch *batch, int *n_launches, int *shapes,
 /* Free a batch (waits for its runs).  NULL is accepted. */
 int mpnl_batch_destroy(mpnl_ctx *ctx, mpnl_batch *batch);
 
+/* ---- serving: continuous batching of arriving slot jobs -------------------- */
+/* The detector run as a service (motivated by the centralised DU serving
+   many radio units in the paper's introduction): slot-detection jobs arrive
+   over time, wait for admission, are merged into launches and complete
+   asynchronously.  The scheduler is host code behind an executor interface;
+   the device executor runs each launch as one mpnl_detect_batch() on its own
+   stream, so launches overlap on the GPU, and times completion with events. */
+
+typedef struct mpnl_server mpnl_server;
+
+typedef struct {
+    size_t hbm_budget;   /* device bytes that admitted jobs may hold together,
+                            counted with mpnl_job_bytes() (0: no limit)      */
+    int max_batch_jobs;  /* most jobs merged into one launch (>= 1)         */
+    int max_inflight;    /* most launches on the device at once (1..8)      */
+    int max_queue;       /* most jobs waiting for admission; an arrival past
+                            it is rejected (0: no limit)                    */
+    double deadline_us;  /* latency target (arrival to completion)          */
+    int drop_late;       /* 1: a job that has already waited past the
+                            deadline when it would be admitted is dropped   */
+} mpnl_server_config;
+
+/* job outcomes */
+#define MPNL_JOB_DONE 0
+#define MPNL_JOB_REJECTED 1  /* queue full, or larger than the budget      */
+#define MPNL_JOB_DROPPED 2   /* past the deadline before admission         */
+#define MPNL_JOB_FAILED 3    /* its launch returned an error (see error)   */
+
+typedef struct {
+    int64_t id;
+    int status;          /* MPNL_JOB_*                                      */
+    int error;           /* MPNL_* code when FAILED, else MPNL_OK           */
+    double arrival_us;   /* server clock                                    */
+    double start_us;     /* launch enqueued (admission)                     */
+    double done_us;      /* device completion (or decision time)            */
+} mpnl_completion;
+
+/* Device bytes a job holds while it runs (slot state, rotated vectors,
+   partial results); the unit of the server's budget.  0 for an invalid
+   shape. */
+size_t mpnl_job_bytes(int S, int T, int M, int N, int mod, int n_paths);
+
+/* Errors: MPNL_E_INVAL (null, max_batch_jobs < 1, max_inflight outside
+   1..8, negative limits), MPNL_E_HIP, MPNL_E_NOMEM. */
+int mpnl_server_create(mpnl_ctx *ctx, const mpnl_server_config *cfg,
+                       mpnl_server **srv);
+/* Server clock in microseconds (steady host clock, 0 at creation). */
+double mpnl_server_now_us(const mpnl_server *srv);
+/* Queue a job that arrived at arrival_us (server clock).  The job's
+   buffers must stay valid until its completion is polled.  Shape errors are
+   returned at once (nothing queued); a rejection is reported through
+   mpnl_server_poll(). */
+int mpnl_server_submit(mpnl_server *srv, const mpnl_job *job, int64_t id,
+                       double arrival_us);
+/* Advance the scheduler: retire finished launches, admit waiting jobs into
+   new launches while launch slots and budget allow, and return up to max
+   completions (n_done receives their number).  Never blocks. */
+int mpnl_server_poll(mpnl_server *srv, mpnl_completion *done, int max,
+                     int *n_done);
+/* Jobs not yet completed (waiting + running). */
+int mpnl_server_pending(const mpnl_server *srv);
+/* Drive n_jobs Poisson arrivals (rate_hz, exponential gaps from a seeded
+   64-bit generator), each a uniformly drawn entry of pool, through the
+   server, polling until every job has completed; out[i] receives job i's
+   completion and entry[i] (entry may be NULL) its pool index.  Several jobs
+   may use one pool entry (and its output buffer).  The server must be idle
+   (MPNL_E_INVAL otherwise). */
+int mpnl_server_run_poisson(mpnl_server *srv, const mpnl_job *pool, int pool_n,
+                            int n_jobs, double rate_hz, uint64_t seed,
+                            mpnl_completion *out, int32_t *entry);
+/* Waits for running launches, then frees the server.  NULL is accepted. */
+int mpnl_server_destroy(mpnl_server *srv);
+
+/* The same scheduler on a virtual clock with a modelled device, for tests of
+   the serving logic without a GPU.  A launch takes launch_us +
+   per_vector_us * (its S * T sum) (+ slow_extra_us if it holds job
+   slow_job) and launches run one after another; launch number fail_launch
+   (0-based, -1 for none) fails with MPNL_E_HIP.  jobs must be sorted by
+   arrival; out[i] receives job i's completion; n_launches (may be NULL)
+   receives the number of launches. */
+typedef struct {
+    int64_t id;
+    double arrival_us;
+    size_t bytes;
+    int64_t vectors;
+} mpnl_sim_job;
+
+typedef struct {
+    double launch_us;
+    double per_vector_us;
+    int fail_launch;
+    int64_t slow_job;
+    double slow_extra_us;
+} mpnl_sim_device;
+
+int mpnl_sched_simulate(const mpnl_server_config *cfg, const mpnl_sim_device *dev,
+                        const mpnl_sim_job *jobs, int n_jobs,
+                        mpnl_completion *out, int *n_launches);
+
 #ifdef __cplusplus
 }
 #endif

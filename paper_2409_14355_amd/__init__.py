@@ -35,10 +35,37 @@ EXPORTED = (
     "mpnl_slot_detect", "mpnl_slot_detect_soft", "mpnl_slot_release", "mpnl_slot_export",
     "mpnl_slot_info", "mpnl_detect_batch", "mpnl_profile_enable", "mpnl_profile_collect",
     "mpnl_batch_create", "mpnl_batch_run", "mpnl_batch_info", "mpnl_batch_destroy",
+    "mpnl_job_bytes", "mpnl_server_create", "mpnl_server_now_us", "mpnl_server_submit",
+    "mpnl_server_poll", "mpnl_server_pending", "mpnl_server_run_poisson", "mpnl_server_destroy",
+    "mpnl_sched_simulate",
 )
+MPNL_JOB_DONE, MPNL_JOB_REJECTED, MPNL_JOB_DROPPED, MPNL_JOB_FAILED = 0, 1, 2, 3
 MPNL_BATCH_AUTOTUNE = 1
 MPNL_STAGE_SQRD, MPNL_STAGE_POSVEC, MPNL_STAGE_ROTATE, MPNL_STAGE_PATHS = 0, 1, 2, 3
 STAGE_NAMES = ("sqrd", "posvec", "rotate", "paths")
+
+
+class mpnl_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_batch_jobs", ctypes.c_int),
+                ("max_inflight", ctypes.c_int), ("max_queue", ctypes.c_int),
+                ("deadline_us", ctypes.c_double), ("drop_late", ctypes.c_int)]
+
+
+class mpnl_completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int), ("error", ctypes.c_int),
+                ("arrival_us", ctypes.c_double), ("start_us", ctypes.c_double),
+                ("done_us", ctypes.c_double)]
+
+
+class mpnl_sim_job(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("arrival_us", ctypes.c_double), ("bytes", ctypes.c_size_t),
+                ("vectors", ctypes.c_int64)]
+
+
+class mpnl_sim_device(ctypes.Structure):
+    _fields_ = [("launch_us", ctypes.c_double), ("per_vector_us", ctypes.c_double),
+                ("fail_launch", ctypes.c_int), ("slow_job", ctypes.c_int64),
+                ("slow_extra_us", ctypes.c_double)]
 
 
 class MpnlError(RuntimeError):
@@ -86,6 +113,21 @@ def lib() -> ctypes.CDLL:
     L.mpnl_batch_run.argtypes = [vp, vp, ctypes.POINTER(mpnl_job), vp]
     L.mpnl_batch_info.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), ip]
     L.mpnl_batch_destroy.argtypes = [vp, vp]
+    cfgp = ctypes.POINTER(mpnl_server_config)
+    compp = ctypes.POINTER(mpnl_completion)
+    L.mpnl_job_bytes.argtypes = [ip] * 6
+    L.mpnl_job_bytes.restype = sz
+    L.mpnl_server_create.argtypes = [vp, cfgp, ctypes.POINTER(vp)]
+    L.mpnl_server_now_us.argtypes = [vp]
+    L.mpnl_server_now_us.restype = ctypes.c_double
+    L.mpnl_server_submit.argtypes = [vp, ctypes.POINTER(mpnl_job), ctypes.c_int64, ctypes.c_double]
+    L.mpnl_server_poll.argtypes = [vp, compp, ip, ctypes.POINTER(ip)]
+    L.mpnl_server_pending.argtypes = [vp]
+    L.mpnl_server_run_poisson.argtypes = [vp, ctypes.POINTER(mpnl_job), ip, ip, ctypes.c_double,
+                                          ctypes.c_uint64, compp, ctypes.POINTER(ctypes.c_int32)]
+    L.mpnl_server_destroy.argtypes = [vp]
+    L.mpnl_sched_simulate.argtypes = [cfgp, ctypes.POINTER(mpnl_sim_device), ctypes.POINTER(mpnl_sim_job),
+                                      ip, compp, ctypes.POINTER(ip)]
     L.mpnl_profile_enable.argtypes = [vp, ip]
     L.mpnl_profile_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ip)]
     _lib = L
@@ -385,6 +427,89 @@ class BatchPlan:
     def close(self):
         if self.handle and self.ctx.handle:
             mpnl_batch_destroy(self.ctx.handle, self.handle)
+        self.handle = 0
+
+
+def server_config(hbm_budget: int = 0, max_batch_jobs: int = 8, max_inflight: int = 2,
+                  max_queue: int = 0, deadline_us: float = 500.0, drop_late: bool = False):
+    return mpnl_server_config(hbm_budget, max_batch_jobs, max_inflight, max_queue, deadline_us,
+                              1 if drop_late else 0)
+
+
+def _completions(arr) -> list[dict]:
+    return [dict(id=c.id, status=c.status, error=c.error, arrival_us=c.arrival_us, start_us=c.start_us,
+                 done_us=c.done_us) for c in arr]
+
+
+def mpnl_job_bytes(S: int, T: int, M: int, N: int, mod: int, n_paths: int) -> int:
+    return int(lib().mpnl_job_bytes(S, T, M, N, mod, n_paths))
+
+
+def mpnl_sched_simulate(cfg: mpnl_server_config, jobs: Sequence[dict], launch_us: float = 5.0,
+                        per_vector_us: float = 0.0, fail_launch: int = -1, slow_job: int = -1,
+                        slow_extra_us: float = 0.0):
+    """Scheduler on a virtual clock with a modelled device.  jobs: dicts
+    {arrival_us, bytes, vectors} in arrival order (ids are their positions).
+    -> (completions by id, number of launches)."""
+    arr = (mpnl_sim_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = mpnl_sim_job(i, j["arrival_us"], j.get("bytes", 0), j.get("vectors", 0))
+    dev = mpnl_sim_device(launch_us, per_vector_us, fail_launch, slow_job, slow_extra_us)
+    out = (mpnl_completion * max(len(jobs), 1))()
+    n = ctypes.c_int()
+    _check(lib().mpnl_sched_simulate(ctypes.byref(cfg), ctypes.byref(dev), arr, len(jobs), out,
+                                     ctypes.byref(n)), "mpnl_sched_simulate")
+    return _completions(out[:len(jobs)]), n.value
+
+
+class Server:
+    """Continuous-batching detection service on one context."""
+
+    def __init__(self, ctx: "Context", cfg: mpnl_server_config):
+        self.ctx = ctx
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        _check(lib().mpnl_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), "mpnl_server_create")
+        self.handle = h.value
+
+    def now_us(self) -> float:
+        return lib().mpnl_server_now_us(self.handle)
+
+    def submit(self, job: dict, id: int, arrival_us: Optional[float] = None):
+        arr = _job_array([job])
+        t = self.now_us() if arrival_us is None else arrival_us
+        _check(lib().mpnl_server_submit(self.handle, arr, id, t), "mpnl_server_submit")
+
+    def poll(self, max_n: int = 256) -> list[dict]:
+        out = (mpnl_completion * max_n)()
+        n = ctypes.c_int()
+        _check(lib().mpnl_server_poll(self.handle, out, max_n, ctypes.byref(n)), "mpnl_server_poll")
+        return _completions(out[:n.value])
+
+    def pending(self) -> int:
+        return lib().mpnl_server_pending(self.handle)
+
+    def drain(self) -> list[dict]:
+        got = []
+        while self.pending() > 0:
+            got += self.poll()
+        return got
+
+    def run_poisson(self, pool: Sequence[dict], n_jobs: int, rate_hz: float, seed: int) -> list[dict]:
+        """-> completions by job id, each with the pool index of the job ("entry")."""
+        arr = _job_array(pool)
+        out = (mpnl_completion * max(n_jobs, 1))()
+        ent = (ctypes.c_int32 * max(n_jobs, 1))()
+        _check(lib().mpnl_server_run_poisson(self.handle, arr, len(pool), n_jobs, rate_hz, seed, out, ent),
+               "mpnl_server_run_poisson")
+        comp = _completions(out[:n_jobs])
+        for c, e in zip(comp, ent[:n_jobs]):
+            c["entry"] = e
+        return comp
+
+    def close(self):
+        if self.handle:
+            lib().mpnl_server_destroy(self.handle)
         self.handle = 0
 
 

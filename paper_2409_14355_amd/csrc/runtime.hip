@@ -13,6 +13,7 @@
 
 #include "device_common.h"
 #include "kernels.h"
+#include "runtime_internal.h"
 
 namespace {
 
@@ -46,9 +47,16 @@ struct mpnl_ctx {
     std::vector<Block> blocks;
     std::vector<mpnl_slot *> slots;
     std::vector<mpnl_batch *> batches;
-    void *pinned = nullptr;  // staging for batch job tables
-    size_t pinned_size = 0;
-    hipEvent_t pinned_ev = nullptr;
+    // ring of pinned staging buffers for batch job tables: a buffer is
+    // rewritten only once the upload that last read it has run
+    struct Staging {
+        void *ptr = nullptr;
+        size_t size = 0;
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    };
+    Staging staging[4];
+    int staging_next = 0;
     // kernel timers
     bool prof = false;
     struct Timed {
@@ -273,6 +281,46 @@ SlotLayout slot_layout(int S, int M, int N, int K, int NP, bool rec_global)
     return L;
 }
 
+}  // namespace
+
+namespace mpnl {
+
+int validate_job_shape(const mpnl_job &j)
+{
+    if (j.T <= 0)
+        return MPNL_E_INVAL;
+    const int rc = validate_shape(j.S, j.M, j.N, j.mod, j.n_paths);
+    if (rc != MPNL_OK)
+        return rc;
+    if ((long long)j.S * j.T > INT_MAX / 4)
+        return MPNL_E_UNSUPPORTED;
+    return MPNL_OK;
+}
+
+int context_device(const mpnl_ctx *ctx)
+{
+    return ctx->device;
+}
+
+size_t job_device_bytes(const mpnl_job &j)
+{
+    if (validate_job_shape(j) != MPNL_OK)
+        return 0;
+    const int K = (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
+    const int NP = (j.N + 3) / 4 * 4;
+    const SlotLayout L = slot_layout(j.S, j.M, j.N, K, NP, !posvec_rec_fits_lds(j.N, K));
+    SlotDev sd{};
+    sd.S = j.S;
+    sd.N = j.N;
+    sd.K = K;
+    return align_up(L.total) + align_up((size_t)j.T * j.S * j.N * sizeof(float2)) +
+           align_up(path_partial_bytes(sd, j.T)) + align_up(sizeof(JobDev));
+}
+
+}  // namespace mpnl
+
+namespace {
+
 int prepare_impl(mpnl_ctx *ctx, const void *H, int S, int M, int N, int mod, int n_paths,
                  hipStream_t st, mpnl_slot **out)
 {
@@ -416,10 +464,12 @@ int mpnl_destroy(mpnl_ctx *ctx)
         if (b.ev)
             (void)hipEventDestroy(b.ev);
     }
-    if (ctx->pinned)
-        (void)hipHostFree(ctx->pinned);
-    if (ctx->pinned_ev)
-        (void)hipEventDestroy(ctx->pinned_ev);
+    for (auto &sg : ctx->staging) {
+        if (sg.ptr)
+            (void)hipHostFree(sg.ptr);
+        if (sg.ev)
+            (void)hipEventDestroy(sg.ev);
+    }
     for (auto &t : ctx->timed) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
@@ -690,21 +740,32 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
             goff[q] = table_bytes;
             table_bytes += align_up(groups[q].idx.size() * sizeof(mpnl::JobDev));
         }
-        if (ctx->pinned_ev && hipEventSynchronize(ctx->pinned_ev) != hipSuccess)
-            rc = MPNL_E_HIP;
-        if (rc == MPNL_OK && ctx->pinned_size < table_bytes) {
-            if (ctx->pinned)
-                (void)hipHostFree(ctx->pinned);
-            ctx->pinned = nullptr;
-            ctx->pinned_size = 0;
-            hipError_t e = hipHostMalloc(&ctx->pinned, table_bytes, hipHostMallocDefault);
+        // staging buffer: the first idle one of the ring, else wait for the oldest
+        mpnl_ctx::Staging *sg = nullptr;
+        for (int k = 0; k < 4 && !sg; ++k) {
+            mpnl_ctx::Staging &c = ctx->staging[(ctx->staging_next + k) % 4];
+            if (!c.pending || hipEventQuery(c.ev) == hipSuccess)
+                sg = &c;
+        }
+        if (!sg) {
+            sg = &ctx->staging[ctx->staging_next];
+            if (hipEventSynchronize(sg->ev) != hipSuccess)
+                rc = MPNL_E_HIP;
+        }
+        ctx->staging_next = (int)(sg - ctx->staging + 1) % 4;
+        if (rc == MPNL_OK && sg->size < table_bytes) {
+            if (sg->ptr)
+                (void)hipHostFree(sg->ptr);
+            sg->ptr = nullptr;
+            sg->size = 0;
+            hipError_t e = hipHostMalloc(&sg->ptr, table_bytes, hipHostMallocDefault);
             if (e != hipSuccess)
                 rc = hip_fail(ctx, e);
             else
-                ctx->pinned_size = table_bytes;
+                sg->size = table_bytes;
         }
-        if (rc == MPNL_OK && !ctx->pinned_ev) {
-            hipError_t e = hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming);
+        if (rc == MPNL_OK && !sg->ev) {
+            hipError_t e = hipEventCreateWithFlags(&sg->ev, hipEventDisableTiming);
             if (e != hipSuccess)
                 rc = hip_fail(ctx, e);
         }
@@ -712,7 +773,7 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
         if (rc == MPNL_OK && !groups.empty())
             rc = pool_alloc(ctx, table_bytes, st, &tblk);
         if (rc == MPNL_OK && !groups.empty()) {
-            char *host = (char *)ctx->pinned;
+            char *host = (char *)sg->ptr;
             char *dev = (char *)ctx->blocks[tblk].ptr;
             std::vector<int> items(groups.size()), threads(groups.size());
             for (size_t q = 0; q < groups.size(); ++q) {
@@ -743,7 +804,8 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
             }
             hipError_t e = hipMemcpyAsync(dev, host, table_bytes, hipMemcpyHostToDevice, st);
             if (e == hipSuccess)
-                e = hipEventRecord(ctx->pinned_ev, st);
+                e = hipEventRecord(sg->ev, st);
+            sg->pending = e == hipSuccess;
             for (size_t q = 0; q < groups.size() && e == hipSuccess; ++q) {
                 const mpnl::JobDev *jd = (const mpnl::JobDev *)(dev + goff[q]);
                 StageTimer tm(ctx, MPNL_STAGE_PATHS, st);

@@ -1,0 +1,173 @@
+"""Serving scheduler logic on a virtual clock (modelled device, no GPU).
+
+The scheduler is the one the device server runs; here its executor models a
+device that runs launches one after another, each taking
+launch_us + per_vector_us * vectors, with forced failures and slow jobs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2409_14355_amd as mp
+
+DONE, REJ, DROP, FAIL = mp.MPNL_JOB_DONE, mp.MPNL_JOB_REJECTED, mp.MPNL_JOB_DROPPED, mp.MPNL_JOB_FAILED
+
+
+def _check_invariants(jobs, comp):
+    assert len(comp) == len(jobs)
+    for i, c in enumerate(comp):
+        assert c["id"] == i
+        assert c["arrival_us"] == pytest.approx(jobs[i]["arrival_us"])
+        assert c["done_us"] >= c["start_us"] >= c["arrival_us"] - 1e-9
+
+
+def test_single_job_latency_is_the_launch():
+    cfg = mp.server_config(max_batch_jobs=4, max_inflight=1)
+    jobs = [dict(arrival_us=10.0, bytes=100, vectors=1000)]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=5.0, per_vector_us=0.01)
+    _check_invariants(jobs, comp)
+    assert nl == 1 and comp[0]["status"] == DONE
+    assert comp[0]["start_us"] == pytest.approx(10.0)
+    assert comp[0]["done_us"] == pytest.approx(10.0 + 5.0 + 10.0)
+
+
+def test_continuous_batching_merges_jobs_that_wait():
+    """Jobs that arrive while the only launch slot is busy go together into
+    the next launch."""
+    cfg = mp.server_config(max_batch_jobs=16, max_inflight=1)
+    jobs = [dict(arrival_us=0.0, bytes=1, vectors=100)] + \
+           [dict(arrival_us=1.0 + i, bytes=1, vectors=100) for i in range(5)]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=50.0, per_vector_us=0.0)
+    _check_invariants(jobs, comp)
+    assert nl == 2
+    assert all(c["status"] == DONE for c in comp)
+    assert comp[0]["done_us"] == pytest.approx(50.0)
+    # the five late arrivals start together when the first launch ends
+    assert {round(c["start_us"], 6) for c in comp[1:]} == {50.0}
+    assert all(c["done_us"] == pytest.approx(100.0) for c in comp[1:])
+
+
+def test_batch_size_limit():
+    cfg = mp.server_config(max_batch_jobs=3, max_inflight=1)
+    jobs = [dict(arrival_us=0.0, bytes=1, vectors=10) for _ in range(10)]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=1.0)
+    _check_invariants(jobs, comp)
+    assert nl == math.ceil(10 / 3)
+    starts = sorted({c["start_us"] for c in comp})
+    assert len(starts) == nl
+
+
+def test_several_launches_in_flight_overlap_in_the_queue():
+    """With two launch slots a second launch is enqueued while the first runs
+    (the modelled device still runs them one after the other)."""
+    cfg = mp.server_config(max_batch_jobs=1, max_inflight=2)
+    jobs = [dict(arrival_us=0.0, bytes=1, vectors=0), dict(arrival_us=1.0, bytes=1, vectors=0),
+            dict(arrival_us=2.0, bytes=1, vectors=0)]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=10.0)
+    _check_invariants(jobs, comp)
+    assert comp[1]["start_us"] == pytest.approx(1.0)       # enqueued at once
+    assert comp[1]["done_us"] == pytest.approx(20.0)       # runs after the first
+    assert comp[2]["start_us"] == pytest.approx(10.0)      # waits for a free slot
+    assert comp[2]["done_us"] == pytest.approx(30.0)
+
+
+def test_budget_admission_serialises_and_rejects_oversize():
+    cfg = mp.server_config(hbm_budget=1000, max_batch_jobs=8, max_inflight=4)
+    jobs = [dict(arrival_us=0.0, bytes=600, vectors=10) for _ in range(4)] + \
+           [dict(arrival_us=1.0, bytes=5000, vectors=10)]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=10.0)
+    _check_invariants(jobs, comp)
+    assert comp[4]["status"] == REJ
+    done = [c for c in comp[:4]]
+    assert all(c["status"] == DONE for c in done)
+    # 600 + 600 > 1000: never two of them admitted together
+    spans = sorted((c["start_us"], c["done_us"]) for c in done)
+    for (s0, d0), (s1, d1) in zip(spans, spans[1:]):
+        assert s1 >= d0 - 1e-9
+    assert nl == 4
+
+
+def test_budget_fits_two_jobs_per_launch():
+    cfg = mp.server_config(hbm_budget=1000, max_batch_jobs=8, max_inflight=1)
+    jobs = [dict(arrival_us=0.0, bytes=500, vectors=10) for _ in range(6)]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=10.0)
+    assert nl == 3 and all(c["status"] == DONE for c in comp)
+
+
+def test_queue_limit_rejects_a_burst():
+    cfg = mp.server_config(max_batch_jobs=1, max_inflight=1, max_queue=5)
+    jobs = [dict(arrival_us=0.0, bytes=1, vectors=0) for _ in range(20)]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=10.0)
+    _check_invariants(jobs, comp)
+    st = np.array([c["status"] for c in comp])
+    # all arrive before the first admission: five wait, the rest are rejected
+    assert (st == REJ).sum() == 15 and (st == DONE).sum() == 5
+
+
+def test_drop_late_keeps_admitted_jobs_within_deadline():
+    cfg = mp.server_config(max_batch_jobs=1, max_inflight=1, deadline_us=100.0, drop_late=True)
+    rng = np.random.default_rng(7)
+    t = np.cumsum(rng.exponential(10.0, size=200))  # 100 k jobs/s offered
+    jobs = [dict(arrival_us=float(x), bytes=1, vectors=1000) for x in t]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=20.0, per_vector_us=0.02)  # 40 us per job
+    _check_invariants(jobs, comp)
+    st = np.array([c["status"] for c in comp])
+    assert (st == DROP).sum() > 0 and (st == DONE).sum() > 0
+    for c in comp:
+        if c["status"] == DONE:
+            assert c["start_us"] - c["arrival_us"] <= 100.0 + 1e-9
+        if c["status"] == DROP:
+            assert c["start_us"] - c["arrival_us"] > 100.0
+
+
+def test_without_drop_every_job_runs_in_arrival_order():
+    cfg = mp.server_config(max_batch_jobs=2, max_inflight=1, deadline_us=1.0)
+    rng = np.random.default_rng(8)
+    t = np.cumsum(rng.exponential(5.0, size=100))
+    jobs = [dict(arrival_us=float(x), bytes=1, vectors=100) for x in t]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=3.0, per_vector_us=0.05)
+    _check_invariants(jobs, comp)
+    assert all(c["status"] == DONE for c in comp)
+    starts = [c["start_us"] for c in comp]
+    assert starts == sorted(starts)  # FIFO
+
+
+def test_failed_launch_fails_only_its_jobs():
+    cfg = mp.server_config(max_batch_jobs=2, max_inflight=1)
+    jobs = [dict(arrival_us=float(i), bytes=1, vectors=10) for i in range(6)]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=10.0, fail_launch=1)
+    _check_invariants(jobs, comp)
+    failed = [c for c in comp if c["status"] == FAIL]
+    assert 1 <= len(failed) <= 2
+    assert all(c["error"] == mp.MPNL_E_HIP for c in failed)
+    assert all(c["status"] == DONE for c in comp if c not in failed)
+
+
+def test_slow_job_delays_the_jobs_behind_it():
+    cfg = mp.server_config(max_batch_jobs=1, max_inflight=1)
+    jobs = [dict(arrival_us=float(i), bytes=1, vectors=0) for i in range(4)]
+    fast, _ = mp.mpnl_sched_simulate(cfg, jobs, launch_us=10.0)
+    slow, _ = mp.mpnl_sched_simulate(cfg, jobs, launch_us=10.0, slow_job=1, slow_extra_us=500.0)
+    assert slow[0]["done_us"] == pytest.approx(fast[0]["done_us"])
+    for i in (1, 2, 3):
+        assert slow[i]["done_us"] == pytest.approx(fast[i]["done_us"] + 500.0)
+
+
+def test_bad_configs_are_refused():
+    for cfg in (mp.server_config(max_batch_jobs=0), mp.server_config(max_inflight=0),
+                mp.server_config(max_inflight=9), mp.server_config(max_queue=-1)):
+        with pytest.raises(mp.MpnlError) as ei:
+            mp.mpnl_sched_simulate(cfg, [dict(arrival_us=0.0)])
+        assert ei.value.code == mp.MPNL_E_INVAL
+    with pytest.raises(mp.MpnlError):  # arrivals out of order
+        mp.mpnl_sched_simulate(mp.server_config(), [dict(arrival_us=5.0), dict(arrival_us=1.0)])
+
+
+def test_job_bytes_grows_with_the_job_and_rejects_bad_shapes():
+    a = mp.mpnl_job_bytes(100, 14, 16, 16, 4, 64)
+    b = mp.mpnl_job_bytes(200, 14, 16, 16, 4, 64)
+    c = mp.mpnl_job_bytes(100, 14, 16, 16, 4, 256)
+    assert 0 < a < b and a < c
+    assert mp.mpnl_job_bytes(100, 14, 4, 8, 4, 64) == 0   # N > M
+    assert mp.mpnl_job_bytes(0, 14, 4, 4, 4, 64) == 0
