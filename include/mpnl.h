@@ -210,6 +210,20 @@ typedef struct mpnl_job {
 int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs,
                       void *stream);
 
+/* ---- linear MMSE, the paper's comparison detector ---------------------------- */
+
+/* Linear MMSE detection (the comparison detector of Sec. I and the baseline
+   of Sec. III-B): per subcarrier x = (H^H H + sigma2 I)^-1 H^H y, each x_k
+   divided by (W H)_kk (unbiased), then the closest constellation point.
+   Same layouts as mpnl_detect(); no permutation (out is in user order).
+   Works for N > M (overloaded) when sigma2 > 0; sigma2 = 0 is zero-forcing.
+   FP32 throughout.  Errors: MPNL_E_INVAL (null, sizes <= 0, sigma2 < 0 or
+   not finite, sigma2 = 0 with N > M), MPNL_E_UNSUPPORTED (M or N above 32,
+   bad mod), MPNL_E_HIP. */
+int mpnl_mmse_detect(mpnl_ctx *ctx, const void *H, const void *y, int S, int T,
+                     int M, int N, int mod, float sigma2, int32_t *out,
+                     void *stream);
+
 /* ---- planned batch: fixed shapes, one graph replay per run ------------------- */
 
 typedef struct mpnl_batch mpnl_batch;

@@ -59,6 +59,7 @@ def lib():
         L.orc_ml_vector.argtypes = [vp, vp, ip, ip, ip, vp, vp]
         L.orc_zf_vector.argtypes = [vp, vp, ip, ip, ip, vp]
         L.orc_mmse_vector.argtypes = [vp, vp, ip, ip, ip, dp, vp]
+        L.orc_mmse_estimate.argtypes = [vp, vp, ip, ip, dp, vp]
         L.orc_sqrd.argtypes = [vp, ip, ip, vp, vp, vp, vp]
         L.orc_num_vectors.argtypes = [ip, ip]
         L.orc_num_vectors.restype = ctypes.c_long
@@ -121,6 +122,15 @@ def mmse(H, y, bits: int, sigma2: float) -> np.ndarray:
     M, N = H.shape
     out = np.zeros(N, np.int32)
     _check(lib().orc_mmse_vector(_ptr(H), _ptr(y), M, N, bits, float(sigma2), _ptr(out)), "mmse")
+    return out
+
+
+def mmse_estimate(H, y, sigma2: float) -> np.ndarray:
+    """Unbiased MMSE estimate x_k / (W H)_kk before slicing (complex, N)."""
+    H, y = _c128(H), _c128(y)
+    M, N = H.shape
+    out = np.zeros(N, np.complex128)
+    _check(lib().orc_mmse_estimate(_ptr(H), _ptr(y), M, N, float(sigma2), _ptr(out)), "mmse_estimate")
     return out
 
 

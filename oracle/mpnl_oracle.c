@@ -195,13 +195,9 @@ static int solve(cplx *A, cplx *B, int n, int m)
 /* MMSE: W = (H^H H + sigma^2 I)^{-1} H^H, x = W y; the estimate is unbiased */
 /*       before slicing by dividing x_k by (W H)_kk.                         */
 /* ------------------------------------------------------------------------ */
-static int linear_detect(const cplx *H, const cplx *y, int M, int N, int bits,
-                         double sigma2, int unbiased, int32_t *idx_out)
+static int linear_estimate(const cplx *H, const cplx *y, int M, int N, double sigma2,
+                           int unbiased, cplx *x_out)
 {
-    cplx pts[ORC_MAXQ];
-    int nq = orc_constellation(bits, pts);
-    if (nq < 0)
-        return -1;
     cplx *G = malloc(sizeof(cplx) * N * N);
     cplx *B = malloc(sizeof(cplx) * N * (M + 1));
     for (int i = 0; i < N; i++)
@@ -230,12 +226,36 @@ static int linear_detect(const cplx *H, const cplx *y, int M, int N, int bits,
                     g += B[k * (M + 1) + m] * H[m * N + k];
                 x /= g;
             }
-            idx_out[k] = slice(pts, nq, x);
+            x_out[k] = x;
         }
     }
     free(G);
     free(B);
     return rc;
+}
+
+static int linear_detect(const cplx *H, const cplx *y, int M, int N, int bits,
+                         double sigma2, int unbiased, int32_t *idx_out)
+{
+    cplx pts[ORC_MAXQ];
+    int nq = orc_constellation(bits, pts);
+    if (nq < 0 || N < 1 || N > ORC_MAXN)
+        return -1;
+    cplx x[ORC_MAXN];
+    int rc = linear_estimate(H, y, M, N, sigma2, unbiased, x);
+    if (rc == 0)
+        for (int k = 0; k < N; k++)
+            idx_out[k] = slice(pts, nq, x[k]);
+    return rc;
+}
+
+/* The unbiased MMSE estimate itself (before slicing), for decision margins. */
+int orc_mmse_estimate(const cplx *H, const cplx *y, int M, int N, double sigma2,
+                      cplx *x_out)
+{
+    if (N < 1 || N > ORC_MAXN)
+        return -1;
+    return linear_estimate(H, y, M, N, sigma2, 1, x_out);
 }
 
 int orc_zf_vector(const cplx *H, const cplx *y, int M, int N, int bits,

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -824,6 +825,27 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
             release_impl(ctx, slots[i]);
     }
     return rc;
+}
+
+int mpnl_mmse_detect(mpnl_ctx *ctx, const void *H, const void *y, int S, int T, int M, int N, int mod,
+                     float sigma2, int32_t *out, void *stream)
+{
+    if (!ctx || !H || !y || !out || S <= 0 || T <= 0 || M <= 0 || N <= 0)
+        return MPNL_E_INVAL;
+    if (!(sigma2 >= 0.f) || !std::isfinite(sigma2) || (N > M && sigma2 == 0.f))
+        return MPNL_E_INVAL;
+    if (mod != MPNL_QPSK && mod != MPNL_QAM16 && mod != MPNL_QAM64)
+        return MPNL_E_UNSUPPORTED;
+    if (N > MPNL_MAX_USERS || M > MPNL_MAX_ANTENNAS)
+        return MPNL_E_UNSUPPORTED;
+    if ((long long)S * T > INT_MAX / 4 || (long long)T * S * M > INT_MAX / 2)
+        return MPNL_E_UNSUPPORTED;
+    DeviceGuard g(ctx->device);
+    if (!g.ok())
+        return hip_fail(ctx, hipErrorInvalidDevice);
+    const hipError_t e = mpnl::launch_mmse((const float2 *)H, (const float2 *)y, S, T, M, N, mod, sigma2, out,
+                                           (hipStream_t)stream);
+    return e == hipSuccess ? MPNL_OK : hip_fail(ctx, e);
 }
 
 // ---------------------------------------------------------------------------

@@ -317,6 +317,29 @@ def test_mmse_matches_direct_solve_and_zf_limit():
         assert np.array_equal(oracle.mmse(H, y, bits, 1e-12), refz)
 
 
+def test_mmse_estimate_closed_forms():
+    """The unbiased estimate equals W y / (W H)_kk from numpy's solve, and
+    (W H)_kk = 1 - s2 (G^-1)_kk with G = H^H H + s2 I (the identity the GPU
+    MMSE uses); overloaded N > M works with s2 > 0."""
+    for (M, N, seed) in ((8, 6, 116), (16, 16, 117), (4, 8, 118)):
+        sl = synth.make_slot(S=4, T=1, M=M, N=N, bits=4, snr_db=8, seed=(seed,)) if N <= M else None
+        rng = np.random.default_rng(seed)
+        for s in range(4):
+            if sl is not None:
+                H = sl.H[s].astype(np.complex128)
+                y = sl.y[0, s].astype(np.complex128)
+            else:
+                H = (rng.normal(size=(M, N)) + 1j * rng.normal(size=(M, N))) / np.sqrt(2)
+                y = rng.normal(size=M) + 1j * rng.normal(size=M)
+            s2 = 0.2
+            G = H.conj().T @ H + s2 * np.eye(N)
+            W = np.linalg.solve(G, H.conj().T)
+            g = np.diag(W @ H)
+            x = oracle.mmse_estimate(H, y, s2)
+            assert np.allclose(x, (W @ y) / g, rtol=1e-10, atol=1e-12)
+            assert np.allclose(g, 1 - s2 * np.diag(np.linalg.inv(G)), rtol=1e-10, atol=1e-12)
+
+
 def test_zfsic_against_projection():
     """Independent ZF-SIC: null each stream with the least-squares residual."""
     bits = 4
