@@ -39,6 +39,9 @@ CELLS_WORKLOAD = "cells40-U4-32-S300-3276-T14"
 # serving: Poisson arrivals of slot jobs whose shapes follow the 40-cell
 # distribution, Kronecker channel (0.5 / 0.3) at 18 dB, 0.5 ms deadline
 SERVING_WORKLOAD = "serving-poisson20k-cells-kron18"
+# BER against SNR for the 16x16 slot: MPNL (64 and 256 paths) and linear
+# MMSE with 16, 32 and 48 antennas, all on the GPU
+SWEEP_WORKLOAD = "16x16-qam16-S1200-T14-snr-sweep"
 
 
 def path_flops_per_vector(N: int, K: int) -> int:
@@ -71,7 +74,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="16x16-qam16-S1200-T14",
-                    choices=sorted(WORKLOADS) + [CELLS_WORKLOAD, SERVING_WORKLOAD])
+                    choices=sorted(WORKLOADS) + [CELLS_WORKLOAD, SERVING_WORKLOAD, SWEEP_WORKLOAD])
     ap.add_argument("--rate", type=float, default=20000.0, help="serving: offered jobs/s")
     ap.add_argument("--jobs", type=int, default=2000, help="serving: jobs per run")
     ap.add_argument("--no-autotune", action="store_true", help="batch workload: default grid sizes")
@@ -91,6 +94,8 @@ def main() -> int:
         return run_cells(args)
     if args.workload == SERVING_WORKLOAD:
         return run_serving(args)
+    if args.workload == SWEEP_WORKLOAD:
+        return run_sweep(args)
 
     import numpy as np
     import torch
@@ -292,6 +297,72 @@ def run_cells(args) -> int:
                                          f"{len(cells)} cells ({nv} vectors, {dt:.1f} s wall)"}
     plan.close()
     ctx.close()
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def run_sweep(args) -> int:
+    """BER against SNR (10..24 dB) for MPNL with 64 and 256 paths on 16x16,
+    and linear MMSE with 16, 32 and 48 antennas for the same 16 users; up to
+    10 slots per point or until 100 bit errors; plus each detector's
+    throughput on one slot."""
+    import numpy as np
+    import torch
+
+    import paper_2409_14355_amd as mp
+    import synth
+
+    N, bits, S, T = 16, 4, 1200, 14
+    dev = torch.device("cuda:0")
+    ctx = mp.Context(0)
+    dets = [("mpnl64", 16, 64), ("mpnl256", 16, 256), ("mmse16", 16, 0), ("mmse32", 32, 0), ("mmse48", 48, 0)]
+
+    def run_det(name, M, K, Hd, yd, s2, out):
+        if K:
+            ctx.detect(Hd, yd, bits, K, out)
+        else:
+            ctx.mmse(Hd, yd, bits, s2, out)
+
+    table = {}
+    for snr in range(10, 25, 2):
+        row = {}
+        for name, M, K in dets:
+            errs = nbits = slots = 0
+            out = torch.empty((T, S, N), dtype=torch.int32, device=dev)
+            while slots < 10 and errs < 100:
+                sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=float(snr), seed=(4, snr, M, slots))
+                Hd, yd = torch.from_numpy(sl.H).to(dev), torch.from_numpy(sl.y).to(dev)
+                run_det(name, M, K, Hd, yd, sl.sigma2, out)
+                torch.cuda.synchronize()
+                errs += synth.bit_errors(out.cpu().numpy(), sl.s_idx, bits)
+                nbits += sl.s_idx.size * bits
+                slots += 1
+            lo, hi = synth.wilson(errs, nbits)
+            row[name] = {"ber": errs / nbits, "ci95": [lo, hi], "bit_errors": int(errs), "slots": slots}
+        table[str(snr)] = row
+    # throughput of each detector on one slot (16 dB)
+    speed = {}
+    for name, M, K in dets:
+        sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=16.0, seed=(4, 99, M))
+        Hd, yd = torch.from_numpy(sl.H).to(dev), torch.from_numpy(sl.y).to(dev)
+        out = torch.empty((T, S, N), dtype=torch.int32, device=dev)
+        for _ in range(5):
+            run_det(name, M, K, Hd, yd, sl.sigma2, out)
+        torch.cuda.synchronize()
+        reps = 50
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run_det(name, M, K, Hd, yd, sl.sigma2, out)
+        torch.cuda.synchronize()
+        speed[name] = S * T * reps / (time.perf_counter() - t0)
+    ctx.close()
+    res = {"metric": METRIC, "value": speed["mpnl256"], "unit": "vectors/s", "n_gpus": 1, "steps": 50,
+           "warmup": 5, "ms_per_step": S * T / speed["mpnl256"] * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": SWEEP_WORKLOAD, "users": N, "bits_per_symbol": bits, "subcarriers": S,
+                      "symbols": T, "snr_db": list(range(10, 25, 2)), "channel": "iid",
+                      "detectors": [d[0] for d in dets]},
+           "ber": table, "vectors_per_s": speed}
     print(json.dumps(res), flush=True)
     return 0
 

@@ -218,8 +218,8 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs,
    Same layouts as mpnl_detect(); no permutation (out is in user order).
    Works for N > M (overloaded) when sigma2 > 0; sigma2 = 0 is zero-forcing.
    FP32 throughout.  Errors: MPNL_E_INVAL (null, sizes <= 0, sigma2 < 0 or
-   not finite, sigma2 = 0 with N > M), MPNL_E_UNSUPPORTED (M or N above 32,
-   bad mod), MPNL_E_HIP. */
+   not finite, sigma2 = 0 with N > M), MPNL_E_UNSUPPORTED (N above 32, M
+   above 64, bad mod), MPNL_E_HIP. */
 int mpnl_mmse_detect(mpnl_ctx *ctx, const void *H, const void *y, int S, int T,
                      int M, int N, int mod, float sigma2, int32_t *out,
                      void *stream);

@@ -836,7 +836,7 @@ int mpnl_mmse_detect(mpnl_ctx *ctx, const void *H, const void *y, int S, int T, 
         return MPNL_E_INVAL;
     if (mod != MPNL_QPSK && mod != MPNL_QAM16 && mod != MPNL_QAM64)
         return MPNL_E_UNSUPPORTED;
-    if (N > MPNL_MAX_USERS || M > MPNL_MAX_ANTENNAS)
+    if (N > MPNL_MAX_USERS || M > 2 * MPNL_MAX_ANTENNAS)
         return MPNL_E_UNSUPPORTED;
     if ((long long)S * T > INT_MAX / 4 || (long long)T * S * M > INT_MAX / 2)
         return MPNL_E_UNSUPPORTED;

@@ -57,6 +57,8 @@ CASES = [  # S, T, M, N, bits, snr, channel
     (17, 5, 32, 32, 6, 25.0, "iid"),
     (24, 14, 24, 24, 4, 18.0, "kron"),
     (9, 3, 5, 1, 6, 12.0, "iid"),
+    (20, 14, 48, 16, 4, 8.0, "iid"),      # 48 antennas (the comparison's largest array)
+    (11, 2, 64, 32, 4, 10.0, "iid"),
 ]
 
 
@@ -70,7 +72,7 @@ def test_mmse_matches_oracle(ctx, case):
     torch.cuda.synchronize()
     got = got.cpu().numpy()
     pts = oracle.constellation(bits)
-    n_bad = n_near = 0
+    n_near = 0
     for s in range(S):
         for t in range(T):
             ref = oracle.mmse(sl.H[s], sl.y[t, s], bits, sl.sigma2)
@@ -81,7 +83,6 @@ def test_mmse_matches_oracle(ctx, case):
             diff = ref != got[t, s]
             assert near[diff].all(), (s, t, ref, got[t, s], x)
             n_near += int(diff.sum())
-        n_bad += 0
     print(f"{case}: {n_near} of {S * T * N} decisions differ, all near a boundary", flush=True)
     assert n_near <= max(2, 0.01 * S * T * N)
 
@@ -111,5 +112,28 @@ def test_mmse_error_codes(ctx, mp):
     assert L.mpnl_mmse_detect(h, hp, yp, 4, 1, 4, 8, 2, 0.0, op, None) == mp.MPNL_E_INVAL   # N > M, s2 = 0
     assert L.mpnl_mmse_detect(h, hp, yp, 4, 1, 4, 8, 2, -1.0, op, None) == mp.MPNL_E_INVAL
     assert L.mpnl_mmse_detect(h, hp, yp, 4, 1, 4, 8, 3, 0.1, op, None) == mp.MPNL_E_UNSUPPORTED
-    assert L.mpnl_mmse_detect(h, hp, yp, 4, 1, 33, 8, 2, 0.1, op, None) == mp.MPNL_E_UNSUPPORTED
+    assert L.mpnl_mmse_detect(h, hp, yp, 4, 1, 65, 8, 2, 0.1, op, None) == mp.MPNL_E_UNSUPPORTED
+    assert L.mpnl_mmse_detect(h, hp, yp, 4, 1, 40, 33, 2, 0.1, op, None) == mp.MPNL_E_UNSUPPORTED
     assert L.mpnl_mmse_detect(h, None, yp, 4, 1, 4, 8, 2, 0.1, op, None) == mp.MPNL_E_INVAL
+
+
+def test_ber_directions_mpnl_vs_mmse(ctx):
+    """The comparison of the 16-user experiment, directionally: more
+    antennas help MMSE, MPNL on 16 antennas beats MMSE on 16, and 256 paths
+    do not lose to 64 (Wilson 95% intervals)."""
+    _say("ber directions")
+    N, bits, S, T, snr = 16, 4, 400, 14, 4.0
+    ber = {}
+    for name, M, K in (("mpnl64", 16, 64), ("mpnl256", 16, 256), ("mmse16", 16, 0), ("mmse32", 32, 0),
+                       ("mmse48", 48, 0)):
+        sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=snr, seed=(502, M))
+        Hd, yd = _dev(sl.H), _dev(sl.y)
+        out = ctx.detect(Hd, yd, bits, K) if K else ctx.mmse(Hd, yd, bits, sl.sigma2)
+        torch.cuda.synchronize()
+        e = synth.bit_errors(out.cpu().numpy(), sl.s_idx, bits)
+        ber[name] = (e, synth.wilson(e, sl.s_idx.size * bits))
+        print(name, e, ber[name][1], flush=True)
+    assert ber["mmse32"][1][1] < ber["mmse16"][1][0]
+    assert ber["mmse48"][1][1] < ber["mmse32"][1][0]
+    assert ber["mpnl64"][1][1] < ber["mmse16"][1][0]
+    assert ber["mpnl256"][0] <= ber["mpnl64"][0]
