@@ -210,6 +210,21 @@ typedef struct mpnl_job {
 int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs,
                       void *stream);
 
+/* ---- regularised MPNL: overloaded systems (N > M) ---------------------------- */
+
+/* MPNL on the MMSE-extended system H_x = [H; sqrt(sigma2) I_N],
+   y_x = [y; 0]: the same five steps with the metric
+   ||y - H s||^2 + sigma2 ||s||^2 and the MMSE detection order, which also
+   works with more users than antennas (the paper's overloaded regime,
+   Secs. III-IV; the paper gives no method for it, this is one reading).
+   Layouts as mpnl_detect(); needs M + N <= 32 (the extended column height).
+   sigma2 = 0 with N <= M is plain MPNL.  Errors: MPNL_E_INVAL (null, sizes,
+   sigma2 < 0 or not finite, sigma2 = 0 with N > M), MPNL_E_UNSUPPORTED
+   (M + N > 32, bad mod, paths), MPNL_E_NOMEM, MPNL_E_HIP. */
+int mpnl_detect_regularized(mpnl_ctx *ctx, const void *H, const void *y, int S,
+                            int T, int M, int N, int mod, int n_paths,
+                            float sigma2, int32_t *out, void *stream);
+
 /* ---- linear MMSE, the paper's comparison detector ---------------------------- */
 
 /* Linear MMSE detection (the comparison detector of Sec. I and the baseline

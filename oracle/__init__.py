@@ -232,3 +232,20 @@ def detect_slot(method: str, H, y, bits: int, n_paths: int = 1, sigma2: float = 
                                int(nthreads))
     _check(rc, "detect_slot")
     return (out, diag) if want_diag else out
+
+
+def regularized_system(H, y, sigma: float):
+    """The MMSE-extended system of an overloaded (or any) slot:
+    H_x = [H; sigma I_N] (S, M+N, N) and y_x = [y; 0] (T, S, M+N), so that
+    ||y_x - H_x s||^2 = ||y - H s||^2 + sigma^2 ||s||^2.  MPNL on it is the
+    regularised detector for N > M (the paper's overloaded regime,
+    Secs. III-IV, for which it gives no method)."""
+    H, y = _c128(H), _c128(y)
+    S, M, N = H.shape
+    T = y.shape[0]
+    Hx = np.zeros((S, M + N, N), np.complex128)
+    Hx[:, :M] = H
+    Hx[:, M:] = sigma * np.eye(N)
+    yx = np.zeros((T, S, M + N), np.complex128)
+    yx[:, :, :M] = y
+    return Hx, yx

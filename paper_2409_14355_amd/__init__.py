@@ -37,7 +37,7 @@ EXPORTED = (
     "mpnl_batch_create", "mpnl_batch_run", "mpnl_batch_info", "mpnl_batch_destroy",
     "mpnl_job_bytes", "mpnl_server_create", "mpnl_server_now_us", "mpnl_server_submit",
     "mpnl_server_poll", "mpnl_server_pending", "mpnl_server_run_poisson", "mpnl_server_destroy",
-    "mpnl_sched_simulate", "mpnl_mmse_detect",
+    "mpnl_sched_simulate", "mpnl_mmse_detect", "mpnl_detect_regularized",
 )
 MPNL_JOB_DONE, MPNL_JOB_REJECTED, MPNL_JOB_DROPPED, MPNL_JOB_FAILED = 0, 1, 2, 3
 MPNL_BATCH_AUTOTUNE = 1
@@ -114,6 +114,7 @@ def lib() -> ctypes.CDLL:
     L.mpnl_batch_info.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), ip]
     L.mpnl_batch_destroy.argtypes = [vp, vp]
     L.mpnl_mmse_detect.argtypes = [vp, vp, vp, ip, ip, ip, ip, ip, ctypes.c_float, vp, vp]
+    L.mpnl_detect_regularized.argtypes = [vp, vp, vp, ip, ip, ip, ip, ip, ip, ctypes.c_float, vp, vp]
     cfgp = ctypes.POINTER(mpnl_server_config)
     compp = ctypes.POINTER(mpnl_completion)
     L.mpnl_job_bytes.argtypes = [ip] * 6
@@ -291,6 +292,12 @@ def mpnl_mmse_detect(ctx: int, H, y, S: int, T: int, M: int, N: int, mod: int, s
                                   _stream(stream)), "mpnl_mmse_detect")
 
 
+def mpnl_detect_regularized(ctx: int, H, y, S: int, T: int, M: int, N: int, mod: int, n_paths: int,
+                            sigma2: float, out, stream=None) -> None:
+    _check(lib().mpnl_detect_regularized(ctx, _ptr(H), _ptr(y), S, T, M, N, mod, n_paths, float(sigma2),
+                                         _ptr(out), _stream(stream)), "mpnl_detect_regularized")
+
+
 def mpnl_profile_enable(ctx: int, enable: bool) -> None:
     _check(lib().mpnl_profile_enable(ctx, 1 if enable else 0), "mpnl_profile_enable")
 
@@ -394,6 +401,15 @@ class Context:
         if out is None:
             out = torch.empty((T, S, N), dtype=torch.int32, device=H.device)
         mpnl_detect(self.handle, H, y, S, T, M, N, mod, n_paths, out, stream)
+        return out
+
+    def detect_regularized(self, H, y, mod: int, n_paths: int, sigma2: float, out=None, stream=None):
+        """MPNL on [H; sqrt(sigma2) I] (overloaded N > M allowed) -> (T, S, N) int32."""
+        import torch
+        S, T, M, N = _shapes(H, y)
+        if out is None:
+            out = torch.empty((T, S, N), dtype=torch.int32, device=H.device)
+        mpnl_detect_regularized(self.handle, H, y, S, T, M, N, mod, n_paths, sigma2, out, stream)
         return out
 
     def mmse(self, H, y, mod: int, sigma2: float, out=None, stream=None):

@@ -52,6 +52,10 @@ hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_
 hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, float sigma2,
                                    float clip, float *llr, int32_t *out, hipStream_t st);
 // Batched path search over many jobs sharing (NMAX bucket, bits); one persistent launch.
+// H_x = [H; sigma I] ((S, M + N, N)) and y_x = [y; 0] ((T, S, M + N)).
+hipError_t launch_extend(const float2 *H, const float2 *y, int S, int T, int M, int N, float sigma, float2 *Hx,
+                         float2 *yx, hipStream_t st);
+
 // Linear MMSE detection of a whole slot (one wavefront per subcarrier).
 hipError_t launch_mmse(const float2 *H, const float2 *y, int S, int T, int M, int N, int bits, float sigma2,
                        int32_t *out, hipStream_t st);

@@ -625,3 +625,47 @@ hipError_t launch_rotate(const SlotDev &sd, const float2 *y, int T, float2 *yt, 
 }
 
 }  // namespace mpnl
+
+// ============================================================================
+// Regularised (MMSE-extended) system for overloaded detection:
+//     H_x = [H; sigma I_N]  ((M + N) x N per subcarrier),   y_x = [y; 0].
+// ||y_x - H_x s||^2 = ||y - H s||^2 + sigma^2 ||s||^2, so the sorted QR and
+// the path search of H_x give the MMSE-ordered, regularised form of the
+// detector, which also exists when N > M.
+// ============================================================================
+namespace mpnl {
+namespace dev {
+namespace {
+
+__global__ __launch_bounds__(256) void extend_kernel(const float2 *H, const float2 *y, int S, int T, int M, int N,
+                                                     float sigma, float2 *Hx, float2 *yx)
+{
+    const int Mx = M + N;
+    const size_t nH = (size_t)S * Mx * N, ny = (size_t)T * S * Mx;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nH + ny; i += (size_t)gridDim.x * blockDim.x) {
+        if (i < nH) {
+            const size_t s = i / ((size_t)Mx * N);
+            const int r = (int)(i / N % Mx), c = (int)(i % N);
+            Hx[i] = r < M ? H[(s * M + r) * N + c] : make_float2(r - M == c ? sigma : 0.f, 0.f);
+        } else {
+            const size_t j = i - nH;
+            const size_t ts = j / Mx;  // t * S + s
+            const int r = (int)(j % Mx);
+            yx[j] = r < M ? y[ts * M + r] : make_float2(0.f, 0.f);
+        }
+    }
+}
+
+}  // namespace
+}  // namespace dev
+
+hipError_t launch_extend(const float2 *H, const float2 *y, int S, int T, int M, int N, float sigma, float2 *Hx,
+                         float2 *yx, hipStream_t st)
+{
+    const size_t n = (size_t)S * (M + N) * N + (size_t)T * S * (M + N);
+    const int grid = (int)std::min<size_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(dev::extend_kernel, dim3(grid), dim3(256), 0, st, H, y, S, T, M, N, sigma, Hx, yx);
+    return hipGetLastError();
+}
+
+}  // namespace mpnl

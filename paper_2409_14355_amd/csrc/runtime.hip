@@ -827,6 +827,48 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
     return rc;
 }
 
+int mpnl_detect_regularized(mpnl_ctx *ctx, const void *H, const void *y, int S, int T, int M, int N, int mod,
+                            int n_paths, float sigma2, int32_t *out, void *stream)
+{
+    if (!ctx || !H || !y || !out || T <= 0 || M <= 0 || N <= 0 || S <= 0)
+        return MPNL_E_INVAL;
+    if (!(sigma2 >= 0.f) || !std::isfinite(sigma2) || (N > M && sigma2 == 0.f))
+        return MPNL_E_INVAL;
+    if (M + N > MPNL_MAX_ANTENNAS)
+        return MPNL_E_UNSUPPORTED;
+    int rc = validate_shape(S, M + N, N, mod, n_paths);
+    if (rc != MPNL_OK)
+        return rc;
+    if ((long long)T * S * (M + N) > INT_MAX / 2)
+        return MPNL_E_UNSUPPORTED;
+    DeviceGuard g(ctx->device);
+    if (!g.ok())
+        return hip_fail(ctx, hipErrorInvalidDevice);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t hb = align_up((size_t)S * (M + N) * N * sizeof(float2));
+    const size_t yb = align_up((size_t)T * S * (M + N) * sizeof(float2));
+    int blk = -1;
+    rc = pool_alloc(ctx, hb + yb, st, &blk);
+    if (rc != MPNL_OK)
+        return rc;
+    float2 *Hx = (float2 *)ctx->blocks[blk].ptr;
+    float2 *yx = (float2 *)((char *)ctx->blocks[blk].ptr + hb);
+    hipError_t e = mpnl::launch_extend((const float2 *)H, (const float2 *)y, S, T, M, N, std::sqrt(sigma2), Hx, yx,
+                                       st);
+    if (e != hipSuccess) {
+        pool_release(ctx, blk, st);
+        return hip_fail(ctx, e);
+    }
+    mpnl_slot *slot = nullptr;
+    rc = prepare_impl(ctx, Hx, S, M + N, N, mod, n_paths, st, &slot);
+    if (rc == MPNL_OK) {
+        rc = detect_impl(ctx, slot, yx, T, out, st, false, 0.f, 0.f, nullptr);
+        release_impl(ctx, slot);
+    }
+    pool_release(ctx, blk, st);
+    return rc;
+}
+
 int mpnl_mmse_detect(mpnl_ctx *ctx, const void *H, const void *y, int S, int T, int M, int N, int mod,
                      float sigma2, int32_t *out, void *stream)
 {

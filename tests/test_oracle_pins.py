@@ -340,6 +340,35 @@ def test_mmse_estimate_closed_forms():
             assert np.allclose(g, 1 - s2 * np.diag(np.linalg.inv(G)), rtol=1e-10, atol=1e-12)
 
 
+def test_regularized_mpnl_all_paths_is_regularized_ml():
+    """Overloaded N > M: MPNL on [H; sigma I] with every path minimises
+    ||y - H s||^2 + sigma^2 ||s||^2 exactly (numpy brute force)."""
+    rng = np.random.default_rng(119)
+    for (M, N, bits) in ((2, 3, 2), (1, 2, 4), (3, 4, 2)):
+        pts = synth._tx_points(bits)
+        nq = len(pts)
+        cands = np.array(np.meshgrid(*[np.arange(nq)] * N, indexing="ij")).reshape(N, -1).T
+        for trial in range(5):
+            H = (rng.normal(size=(1, M, N)) + 1j * rng.normal(size=(1, M, N))) / np.sqrt(2)
+            s_true = rng.integers(0, nq, size=N)
+            y = (H[0] @ pts[s_true] + 0.3 * (rng.normal(size=M) + 1j * rng.normal(size=M)))[None, None, :]
+            sigma = 0.4
+            Hx, yx = oracle.regularized_system(H, y, sigma)
+            got = oracle.detect_slot("mpnl", Hx, yx, bits, n_paths=nq ** N)[0, 0]
+            X = pts[cands]  # (C, N)
+            cost = np.sum(np.abs(y[0, 0][None, :] - X @ H[0].T) ** 2, axis=1) + sigma ** 2 * np.sum(np.abs(X) ** 2, axis=1)
+            best = cands[np.argmin(cost)]
+            assert np.array_equal(got, best), (M, N, bits, trial)
+
+
+def test_regularized_with_zero_sigma_is_plain_mpnl():
+    sl = synth.make_slot(S=6, T=3, M=8, N=6, bits=4, snr_db=12, seed=(120,))
+    Hx, yx = oracle.regularized_system(sl.H, sl.y, 0.0)
+    a = oracle.detect_slot("mpnl", Hx, yx, 4, n_paths=32)
+    b = oracle.detect_slot("mpnl", sl.H, sl.y, 4, n_paths=32)
+    assert np.array_equal(a, b)
+
+
 def test_zfsic_against_projection():
     """Independent ZF-SIC: null each stream with the least-squares residual."""
     bits = 4
