@@ -42,6 +42,10 @@ SERVING_WORKLOAD = "serving-poisson20k-cells-kron18"
 # BER against SNR for the 16x16 slot: MPNL (64 and 256 paths) and linear
 # MMSE with 16, 32 and 48 antennas, all on the GPU
 SWEEP_WORKLOAD = "16x16-qam16-S1200-T14-snr-sweep"
+# antennas needed per user count for a BER target (analog of the paper's
+# antenna search, Sec. III-B, without coding): regularised MPNL (64 / 256
+# paths, overloaded slots allowed) and linear MMSE, 16-QAM, 20 dB
+ANTENNA_WORKLOAD = "antenna-search-qam16-20dB"
 
 
 def path_flops_per_vector(N: int, K: int) -> int:
@@ -74,7 +78,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="16x16-qam16-S1200-T14",
-                    choices=sorted(WORKLOADS) + [CELLS_WORKLOAD, SERVING_WORKLOAD, SWEEP_WORKLOAD])
+                    choices=sorted(WORKLOADS) + [CELLS_WORKLOAD, SERVING_WORKLOAD, SWEEP_WORKLOAD,
+                                                 ANTENNA_WORKLOAD])
     ap.add_argument("--rate", type=float, default=20000.0, help="serving: offered jobs/s")
     ap.add_argument("--jobs", type=int, default=2000, help="serving: jobs per run")
     ap.add_argument("--no-autotune", action="store_true", help="batch workload: default grid sizes")
@@ -96,6 +101,8 @@ def main() -> int:
         return run_serving(args)
     if args.workload == SWEEP_WORKLOAD:
         return run_sweep(args)
+    if args.workload == ANTENNA_WORKLOAD:
+        return run_antenna_search(args)
 
     import numpy as np
     import torch
@@ -297,6 +304,66 @@ def run_cells(args) -> int:
                                          f"{len(cells)} cells ({nv} vectors, {dt:.1f} s wall)"}
     plan.close()
     ctx.close()
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def antenna_search(ber_of, m_lo: int, m_hi: int, target: float):
+    """Smallest antenna count M in m_lo..m_hi with ber_of(M) <= target, trying
+    M one at a time upwards (as the paper's procedure raises the antennas one
+    by one); None if even m_hi misses the target.  -> (M or None, trace)."""
+    trace = []
+    for M in range(m_lo, m_hi + 1):
+        b = ber_of(M)
+        trace.append((M, b))
+        if b <= target:
+            return M, trace
+    return None, trace
+
+
+def run_antenna_search(args) -> int:
+    import numpy as np
+    import torch
+
+    import paper_2409_14355_amd as mp
+    import synth
+
+    bits, snr, S, T, target = 4, 20.0, 300, 14, 1e-3
+    dev = torch.device("cuda:0")
+    ctx = mp.Context(0)
+
+    def ber_fn(det, N):
+        def f(M):
+            sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=snr, seed=(5, N, M))
+            H, y = torch.from_numpy(sl.H).to(dev), torch.from_numpy(sl.y).to(dev)
+            if det == "mmse":
+                out = ctx.mmse(H, y, bits, sl.sigma2)
+            else:
+                out = ctx.detect_regularized(H, y, bits, int(det[4:]), sl.sigma2)
+            torch.cuda.synchronize()
+            return synth.bit_errors(out.cpu().numpy(), sl.s_idx, bits) / (sl.s_idx.size * bits)
+        return f
+
+    result = {}
+    t0 = time.perf_counter()
+    for N in (2, 4, 8, 12, 16):
+        row = {}
+        for det in ("mpnl64", "mpnl256", "mmse"):
+            m_hi = 64 if det == "mmse" else 32 - N
+            m_lo = 1
+            M, trace = antenna_search(ber_fn(det, N), m_lo, m_hi, target)
+            row[det] = {"antennas": M, "trace": [[m, float(b)] for m, b in trace]}
+        result[str(N)] = row
+    wall = time.perf_counter() - t0
+    ctx.close()
+    res = {"metric": "antennas needed for uncoded BER <= 1e-3", "value": None, "unit": "antennas",
+           "n_gpus": 1, "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": ANTENNA_WORKLOAD, "bits_per_symbol": bits, "snr_db": snr, "subcarriers": S,
+                      "symbols": T, "channel": "iid", "ber_target": target,
+                      "mpnl": "regularised ([H; sigma I]), M + N <= 32"},
+           "antennas_needed": {N: {d: v["antennas"] for d, v in row.items()} for N, row in result.items()},
+           "search": result, "wall_s": wall}
     print(json.dumps(res), flush=True)
     return 0
 

@@ -171,3 +171,16 @@ def test_job_bytes_grows_with_the_job_and_rejects_bad_shapes():
     assert 0 < a < b and a < c
     assert mp.mpnl_job_bytes(100, 14, 4, 8, 4, 64) == 0   # N > M
     assert mp.mpnl_job_bytes(0, 14, 4, 4, 4, 64) == 0
+
+
+def test_antenna_search_takes_the_first_count_meeting_the_target():
+    import bench
+    calls = []
+
+    def ber(M):
+        calls.append(M)
+        return 1.0 / M
+    M, trace = bench.antenna_search(ber, 2, 40, 0.1)
+    assert M == 10 and calls == list(range(2, 11)) and trace[-1] == (10, 0.1)
+    M, trace = bench.antenna_search(lambda m: 1.0, 3, 6, 0.5)
+    assert M is None and [m for m, _ in trace] == [3, 4, 5, 6]
