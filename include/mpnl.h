@@ -84,10 +84,17 @@ typedef struct mpnl_slot mpnl_slot;
 
 /* ---- lifecycle ---------------------------------------------------------- */
 
+/* flags of mpnl_create */
+#define MPNL_CREATE_NO_PRUNE 1u  /* run every path to the last depth.  By
+   default a path-search wavefront stops once all its paths have a partial
+   metric above the metric of path 0 (computed first), since the metric only
+   grows along a path; the detected symbols are the same either way. */
+
 /* Create a context on HIP device `device`.  `hbm_budget_bytes` caps the
    device memory the context may hold for slot state and workspace (0 = no
-   cap).  `flags` must be 0.  On success *ctx receives the context.
-   Errors: MPNL_E_INVAL (ctx NULL, flags != 0), MPNL_E_HIP (bad device). */
+   cap).  `flags`: 0 or MPNL_CREATE_NO_PRUNE.  On success *ctx receives the
+   context.  Errors: MPNL_E_INVAL (ctx NULL, unknown flags), MPNL_E_HIP (bad
+   device). */
 int mpnl_create(mpnl_ctx **ctx, int device, size_t hbm_budget_bytes,
                 unsigned flags);
 

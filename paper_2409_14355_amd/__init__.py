@@ -40,6 +40,7 @@ EXPORTED = (
     "mpnl_sched_simulate", "mpnl_mmse_detect", "mpnl_detect_regularized",
 )
 MPNL_JOB_DONE, MPNL_JOB_REJECTED, MPNL_JOB_DROPPED, MPNL_JOB_FAILED = 0, 1, 2, 3
+MPNL_CREATE_NO_PRUNE = 1
 MPNL_BATCH_AUTOTUNE = 1
 MPNL_STAGE_SQRD, MPNL_STAGE_POSVEC, MPNL_STAGE_ROTATE, MPNL_STAGE_PATHS = 0, 1, 2, 3
 STAGE_NAMES = ("sqrd", "posvec", "rotate", "paths")
@@ -362,9 +363,9 @@ class Slot:
 
 
 class Context:
-    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, prune: bool = True):
         self.device = device
-        self.handle = mpnl_create(device, hbm_budget_bytes, 0)
+        self.handle = mpnl_create(device, hbm_budget_bytes, 0 if prune else MPNL_CREATE_NO_PRUNE)
 
     def close(self):
         if self.handle:

@@ -36,6 +36,7 @@ using cptr = const __attribute__((address_space(4))) T *;
 __device__ __forceinline__ cptr<float> uniform_ptr(const float2 *p) { return (cptr<float>)p; }
 __device__ __forceinline__ cptr<float> uniform_ptr(const float4 *p) { return (cptr<float>)p; }
 __device__ __forceinline__ cptr<uint32_t> uniform_ptr(const uint32_t *p) { return (cptr<uint32_t>)p; }
+__device__ __forceinline__ cptr<float> uniform_ptr(const float *p) { return (cptr<float>)p; }
 
 __device__ __forceinline__ float2 ld2(cptr<float> p, int i) { return make_float2(p[2 * i], p[2 * i + 1]); }
 
@@ -338,6 +339,7 @@ struct PathArgs {
     int32_t *out;          // (T, S, N)
     float *llr;            // (T, S, N, bits) or null
     float *part;           // per path group best (metric, path, decisions) or null
+    float *bound;          // (T, S) metric of path 0 per vector (pruning), or null
     int S, T, N, K, NP;
     float sigma2, clip;
 };
@@ -351,16 +353,25 @@ __device__ __forceinline__ constexpr float code_weight(int d)
     return (d & 3) == 0 ? 1.f : (d & 3) == 1 ? 64.f : (d & 3) == 2 ? 4096.f : 262144.f;
 }
 
-// One SIC descent driven by the position vector in pw.  After each decision
-// the residuals of the depths below are updated, b_e -= R'[d][e] s_d.
-template <int N, int L, int PREC>
-__device__ __forceinline__ float descend(cptr<float> yv, cptr<float> dg, cptr<float> rl,
-                                        cptr<uint32_t> rq, const uint32_t *pw, float *decf)
+// Pruning.  The accumulated metric never decreases along a path, so a path
+// whose partial metric already exceeds the metric of some complete path can
+// no longer be the minimum.  Path 0 (the first choice at every depth) is
+// evaluated per received vector before the search (path_bound_kernel); a
+// wavefront whose paths all exceed that bound, padded by kBoundPad for
+// rounding differences between the two evaluations, stops descending.  The
+// winner and its tie rule are unchanged: every pruned path has a metric
+// strictly above the minimum.
+constexpr float kBoundPad = 1.0001f;
+
+// One SIC descent from the residuals b (yt of the vector) driven by the
+// position vector in pw.  After each decision the residuals of the depths
+// below are updated, b_e -= R'[d][e] s_d.  `prune`: the wave stops once every
+// lane with live = true has a metric above it (all lanes must take part).
+// FIRST: every rank is 1 (path 0), the choice code for higher ranks is left out.
+template <int N, int L, int PREC, bool FIRST = false>
+__device__ __forceinline__ float descend(float2 (&b)[N], cptr<float> dg, cptr<float> rl, cptr<uint32_t> rq,
+                                         const uint32_t *pw, float *decf, float prune, bool live)
 {
-    float2 b[N];
-#pragma unroll
-    for (int d = 0; d < N; ++d)
-        b[d] = ld2(yv, d);
     float metric = 0.f;
 #pragma unroll
     for (int d = 0; d < N; ++d) {
@@ -380,7 +391,8 @@ __device__ __forceinline__ float descend(cptr<float> yv, cptr<float> dg, cptr<fl
             const float dI = zI - lI, dQ = zQ - lQ;
             eI = dI * dI;
             eQ = dQ * dQ;
-            if (k == 2) {
+            if (FIRST) {
+            } else if (k == 2) {
                 // rank 2 is (second I, closest Q) or (closest I, second Q):
                 // every other point is farther than one of the two
                 float mI1, eI1, mQ1, eQ1;
@@ -396,11 +408,13 @@ __device__ __forceinline__ float descend(cptr<float> yv, cptr<float> dg, cptr<fl
             } else if (k == 3 || k == 4) {
                 kth_small<L>(zI, zQ, k, mI, lI, eI, mQ, lQ, eQ);
             }
-            if constexpr (L > 2)
+            if constexpr (L > 2 && !FIRST)
                 kth_wave<L>(k > 4, zI, zQ, k, mI, mQ, eI, eQ);
         }
         metric = fmaf(gw, eI + eQ, metric);
         decf[d >> 2] = fmaf(fmaf(mQ, (float)L, mI), code_weight(d), decf[d >> 2]);
+        if (d + 1 < N && __all(!live || metric > prune))
+            break;
         const float sI = level_of<L>(mI), sQ = level_of<L>(mQ);
         if constexpr (PREC == PREC_FP32) {
 #pragma unroll
@@ -500,7 +514,7 @@ __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cp
                                               cptr<uint32_t> rq, const uint8_t *Pbase,
                                               const uint16_t *order, int K, int NP, int group,
                                               const int32_t *pm, int32_t *o, float *part, float *sm,
-                                              int *sr, int W, int tid, bool active)
+                                              int *sr, int W, int tid, bool active, float prune)
 {
     constexpr int NW = (N + 3) / 4;
     const uint32_t *Pw = (const uint32_t *)Pbase;
@@ -521,7 +535,11 @@ __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cp
 #pragma unroll
         for (int w = 0; w < NW; ++w)
             pw[w] = valid ? Pw[(size_t)r * nw + w] : 0x01010101u;
-        const float m = descend<N, L, PREC>(yv, dg, rl, rq, pw, decf);
+        float2 b[N];
+#pragma unroll
+        for (int d = 0; d < N; ++d)
+            b[d] = ld2(yv, d);
+        const float m = descend<N, L, PREC>(b, dg, rl, rq, pw, decf, prune, valid);
         if (valid) {
             bm = m;
             br = r;
@@ -558,10 +576,11 @@ __global__ __launch_bounds__(256) void path_search_kernel(PathArgs a)
     const size_t v = (size_t)t * a.S + s;
     cptr<uint32_t> rq = a.rq ? uniform_ptr(a.rq + sN * N) : nullptr;
     float *part = a.part ? a.part + (v * gridDim.y + blockIdx.y) * (2 + (N + 3) / 4) : nullptr;
+    const float prune = a.bound ? uniform_ptr(a.bound + v)[0] * kBoundPad : INFINITY;
     search_vector<N, L, PREC>(uniform_ptr(a.yt + v * N), uniform_ptr(a.diag + sN), uniform_ptr(a.rlat + sN * N),
                               rq, a.P + (size_t)s * a.K * a.NP, a.order ? a.order + (size_t)s * a.K : nullptr,
                               a.K, a.NP, blockIdx.y, a.permd + sN, a.out + v * N, part, sm, sr, (int)blockDim.x,
-                              (int)threadIdx.x, true);
+                              (int)threadIdx.x, true, prune);
 }
 
 // Best of the path groups of every received vector (equal metrics: lowest
@@ -623,7 +642,11 @@ __device__ __forceinline__ void soft_vector(const PathArgs &a, int s, int t, uns
             pw[w] = valid ? Pw[(size_t)r * nw + w] : 0x01010101u;
             decf[w] = 0.f;
         }
-        const float m = descend<N, L, PREC_FP32>(yv, dg, rl, nullptr, pw, decf);
+        float2 b[N];
+#pragma unroll
+        for (int d = 0; d < N; ++d)
+            b[d] = ld2(yv, d);
+        const float m = descend<N, L, PREC_FP32>(b, dg, rl, nullptr, pw, decf, INFINITY, valid);
         if (valid) {
             mets[r] = m;
 #pragma unroll
@@ -725,10 +748,81 @@ __global__ __launch_bounds__(256) void path_search_multi_kernel(MultiArgs a)
     const size_t sN = (size_t)s * N;
     const size_t v = (size_t)t * j.S + s;
     cptr<uint32_t> rq = j.rq ? uniform_ptr(j.rq + sN * N) : nullptr;
+    const float prune = j.bound ? uniform_ptr(j.bound + v)[0] * kBoundPad : INFINITY;
     search_vector<N, L, PREC>(uniform_ptr(j.yt + v * N), uniform_ptr(j.diag + sN), uniform_ptr(j.rlat + sN * N), rq,
                               j.P + (size_t)s * j.K * j.NP, j.order ? j.order + (size_t)s * j.K : nullptr, j.K,
                               j.NP, 0, j.permd + sN, j.out + v * N, nullptr, sm, sr, W, (int)threadIdx.x - q * W,
-                              active);
+                              active, prune);
+}
+
+// ============================================================================
+// Pruning bound: the metric of path 0 (first choice at every depth) of every
+// received vector, computed with the same descent as the path search.  A
+// wavefront per (subcarrier, 64 symbols); lane t runs symbol t0 + t (lanes
+// past the last symbol repeat it and write nothing).
+// ============================================================================
+template <int N, int L, int PREC>
+__device__ __forceinline__ void bound_body(const float2 *yt, cptr<float> dg, cptr<float> rl, cptr<uint32_t> rq,
+                                           int S, int T, int s, int t0, float *bound)
+{
+    constexpr int NW = (N + 3) / 4;
+    const int t = t0 + (int)(threadIdx.x & 63u);
+    const int tt = min(t, T - 1);
+    float2 b[N];
+    const float2 *yv = yt + ((size_t)tt * S + s) * N;
+#pragma unroll
+    for (int d = 0; d < N; ++d)
+        b[d] = yv[d];
+    uint32_t pw[NW];
+    float decf[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        pw[w] = 0x01010101u;
+        decf[w] = 0.f;
+    }
+    const float m = descend<N, L, PREC, true>(b, dg, rl, rq, pw, decf, INFINITY, true);
+    if (t < T)
+        bound[(size_t)t * S + s] = m;
+}
+
+// grid: S * ceil(T / 64) wavefronts
+template <int N, int L, int PREC>
+__global__ __launch_bounds__(64) void path_bound_kernel(PathArgs a)
+{
+    const int chunks = (a.T + 63) / 64;
+    const int s = blockIdx.x / chunks, t0 = (blockIdx.x - s * chunks) * 64;
+    const size_t sN = (size_t)s * N;
+    cptr<uint32_t> rq = a.rq ? uniform_ptr(a.rq + sN * N) : nullptr;
+    bound_body<N, L, PREC>(a.yt, uniform_ptr(a.diag + sN), uniform_ptr(a.rlat + sN * N), rq, a.S, a.T, s, t0,
+                           a.bound);
+}
+
+// Many jobs of one (N, L): item = (job, subcarrier, 64-symbol chunk), numbered
+// job by job from JobDev::bound_begin.
+__device__ __forceinline__ int find_bound_job(const JobDev *jobs, int n_jobs, int item)
+{
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].bound_begin <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int N, int L, int PREC>
+__global__ __launch_bounds__(64) void path_bound_multi_kernel(const JobDev *jobs, int n_jobs)
+{
+    const JobDev &j = jobs[find_bound_job(jobs, n_jobs, (int)blockIdx.x)];
+    const int chunks = (j.T + 63) / 64;
+    const int li = (int)blockIdx.x - j.bound_begin;
+    const int s = li / chunks, t0 = (li - s * chunks) * 64;
+    const size_t sN = (size_t)s * N;
+    cptr<uint32_t> rq = j.rq ? uniform_ptr(j.rq + sN * N) : nullptr;
+    bound_body<N, L, PREC>(j.yt, uniform_ptr(j.diag + sN), uniform_ptr(j.rlat + sN * N), rq, j.S, j.T, s, t0,
+                           j.bound);
 }
 
 inline float delta_of(int bits)

@@ -73,6 +73,71 @@ hipError_t path_multi_launch_n30(const dev::MultiArgs &, int, int, int, int, hip
 hipError_t path_multi_launch_n31(const dev::MultiArgs &, int, int, int, int, hipStream_t);
 hipError_t path_multi_launch_n32(const dev::MultiArgs &, int, int, int, int, hipStream_t);
 
+hipError_t path_bound_launch_n1(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n2(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n3(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n4(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n5(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n6(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n7(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n8(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n9(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n10(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n11(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n12(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n13(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n14(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n15(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n16(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n17(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n18(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n19(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n20(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n21(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n22(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n23(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n24(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n25(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n26(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n27(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n28(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n29(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n30(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n31(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_launch_n32(const dev::PathArgs &, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n1(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n2(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n3(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n4(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n5(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n6(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n7(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n8(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n9(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n10(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n11(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n12(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n13(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n14(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n15(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n16(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n17(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n18(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n19(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n20(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n21(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n22(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n23(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n24(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n25(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n26(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n27(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n28(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n29(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n30(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n31(const JobDev *, int, int, int, int, hipStream_t);
+hipError_t path_bound_multi_launch_n32(const JobDev *, int, int, int, int, hipStream_t);
+
 namespace {
 using namespace dev;
 
@@ -147,6 +212,78 @@ const MultiLaunch kMultiLaunch[32] = {
     path_multi_launch_n32,
 };
 
+typedef hipError_t (*BoundLaunch)(const PathArgs &, int, int, hipStream_t);
+const BoundLaunch kBoundLaunch[32] = {
+    path_bound_launch_n1,
+    path_bound_launch_n2,
+    path_bound_launch_n3,
+    path_bound_launch_n4,
+    path_bound_launch_n5,
+    path_bound_launch_n6,
+    path_bound_launch_n7,
+    path_bound_launch_n8,
+    path_bound_launch_n9,
+    path_bound_launch_n10,
+    path_bound_launch_n11,
+    path_bound_launch_n12,
+    path_bound_launch_n13,
+    path_bound_launch_n14,
+    path_bound_launch_n15,
+    path_bound_launch_n16,
+    path_bound_launch_n17,
+    path_bound_launch_n18,
+    path_bound_launch_n19,
+    path_bound_launch_n20,
+    path_bound_launch_n21,
+    path_bound_launch_n22,
+    path_bound_launch_n23,
+    path_bound_launch_n24,
+    path_bound_launch_n25,
+    path_bound_launch_n26,
+    path_bound_launch_n27,
+    path_bound_launch_n28,
+    path_bound_launch_n29,
+    path_bound_launch_n30,
+    path_bound_launch_n31,
+    path_bound_launch_n32,
+};
+
+typedef hipError_t (*BoundMultiLaunch)(const JobDev *, int, int, int, int, hipStream_t);
+const BoundMultiLaunch kBoundMultiLaunch[32] = {
+    path_bound_multi_launch_n1,
+    path_bound_multi_launch_n2,
+    path_bound_multi_launch_n3,
+    path_bound_multi_launch_n4,
+    path_bound_multi_launch_n5,
+    path_bound_multi_launch_n6,
+    path_bound_multi_launch_n7,
+    path_bound_multi_launch_n8,
+    path_bound_multi_launch_n9,
+    path_bound_multi_launch_n10,
+    path_bound_multi_launch_n11,
+    path_bound_multi_launch_n12,
+    path_bound_multi_launch_n13,
+    path_bound_multi_launch_n14,
+    path_bound_multi_launch_n15,
+    path_bound_multi_launch_n16,
+    path_bound_multi_launch_n17,
+    path_bound_multi_launch_n18,
+    path_bound_multi_launch_n19,
+    path_bound_multi_launch_n20,
+    path_bound_multi_launch_n21,
+    path_bound_multi_launch_n22,
+    path_bound_multi_launch_n23,
+    path_bound_multi_launch_n24,
+    path_bound_multi_launch_n25,
+    path_bound_multi_launch_n26,
+    path_bound_multi_launch_n27,
+    path_bound_multi_launch_n28,
+    path_bound_multi_launch_n29,
+    path_bound_multi_launch_n30,
+    path_bound_multi_launch_n31,
+    path_bound_multi_launch_n32,
+};
+
 PathArgs path_args(const SlotDev &sd, const float2 *yt, int T, int32_t *out)
 {
     PathArgs a;
@@ -160,6 +297,7 @@ PathArgs path_args(const SlotDev &sd, const float2 *yt, int T, int32_t *out)
     a.out = out;
     a.llr = nullptr;
     a.part = nullptr;
+    a.bound = nullptr;
     a.S = sd.S;
     a.T = T;
     a.N = sd.N;
@@ -186,12 +324,18 @@ size_t path_partial_bytes(const SlotDev &sd, int T)
 }
 
 hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_t *out,
-                              int precision, float *part, hipStream_t st)
+                              int precision, float *part, float *bound, hipStream_t st)
 {
     if (sd.N < 1 || sd.N > 32)
         return hipErrorInvalidValue;
     PathArgs a = path_args(sd, yt, T, out);
     a.rq = precision == PREC_FP16 ? sd.rlat_h : precision == PREC_BF16 ? sd.rlat_b : nullptr;
+    if (bound != nullptr) {
+        a.bound = bound;
+        const hipError_t eb = kBoundLaunch[sd.N - 1](a, sd.bits, precision, st);
+        if (eb != hipSuccess)
+            return eb;
+    }
     const int groups = (sd.K + 255) / 256;
     if (groups > 1) {
         if (part == nullptr)
@@ -225,6 +369,14 @@ hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, f
     case 24: return soft_launch_nmax24(a, sd.bits, st);
     default: return soft_launch_nmax32(a, sd.bits, st);
     }
+}
+
+hipError_t launch_path_bound_multi(const JobDev *jobs_dev, int n_jobs, int bound_items, int N, int bits,
+                                   int precision, hipStream_t st)
+{
+    if (N < 1 || N > 32 || bound_items < 1)
+        return hipErrorInvalidValue;
+    return kBoundMultiLaunch[N - 1](jobs_dev, n_jobs, bound_items, bits, precision, st);
 }
 
 hipError_t launch_path_search_multi(const JobDev *jobs_dev, int n_jobs, int total_items, int N, int bits,

@@ -35,8 +35,10 @@ struct JobDev {
     const uint8_t *P;
     const uint16_t *order;
     int32_t *out;          // (T, S, N)
+    float *bound;          // (T, S) pruning bound per vector (path 0's metric), or null
     int S, T, N, K, NP;
     int item_begin;        // first global work item of this job
+    int bound_begin;       // first item of this job in the bound launch (S * ceil(T / 64) items a job)
 };
 
 // Kernel launchers (enqueue only; return hipError_t of the launch).
@@ -48,7 +50,7 @@ hipError_t launch_rotate(const SlotDev &sd, const float2 *y, int T, float2 *yt, 
 // paths meet in `part` (path_partial_bytes(); null when K <= 256).
 size_t path_partial_bytes(const SlotDev &sd, int T);
 hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_t *out,
-                              int precision, float *part, hipStream_t st);
+                              int precision, float *part, float *bound, hipStream_t st);
 hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, float sigma2,
                                    float clip, float *llr, int32_t *out, hipStream_t st);
 // Batched path search over many jobs sharing (NMAX bucket, bits); one persistent launch.
@@ -66,6 +68,11 @@ hipError_t launch_mmse(const float2 *H, const float2 *y, int S, int T, int M, in
 // workgroup (threads * vpw <= 256).
 hipError_t launch_path_search_multi(const JobDev *jobs_dev, int n_jobs, int total_items, int N, int bits,
                                     int precision, int threads, int vpw, hipStream_t st);
+// Pruning bounds (path 0's metric per vector) for the jobs of a multi-job
+// launch whose JobDev::bound is set: S * ceil(T / 64) items per job, numbered
+// from JobDev::bound_begin.  Run before launch_path_search_multi.
+hipError_t launch_path_bound_multi(const JobDev *jobs_dev, int n_jobs, int bound_items, int N, int bits,
+                                   int precision, hipStream_t st);
 
 namespace dev {
 struct StageJob;

@@ -264,13 +264,18 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
         for (int q = 0; q < kMaxN / 4; ++q)
             if (q < nw)
                 dst[q] = wvd[q];
-        // sort key: depths with rank >= 3 first, then depths with rank >= 2
-        // (as a double the low bits of the second mask may round; the key
-        // only groups paths, any order is correct)
-        ks = (double)m3 * 4294967296.0 + (double)m2;
+        // sort key: the first depth with a rank >= 2 (paths that leave the
+        // first-choice path early are pruned early, and the pruning stops
+        // whole wavefronts), then the depths with rank >= 3, then a fold of
+        // the depths with rank >= 2 (the key only groups paths; any order is
+        // correct)
+        const uint32_t fd = m2 ? (uint32_t)__builtin_ctz(m2) : (uint32_t)N;
+        const uint32_t m2f = (m2 ^ (m2 >> 15) ^ (m2 >> 30)) & 0x7fffu;
+        ks = (double)fd * 140737488355328.0 + (double)m3 * 32768.0 + (double)m2f;  // 2^47, 2^15
     }
     // Lane order: paths sorted by that key, so that the lanes of one
-    // wavefront need the costly point choices at the same depths.
+    // wavefront leave path 0 at about the same depth and need the costly
+    // point choices at the same depths.
     // order[i] = path run by lane i.  Full bitonic sort of the KP entries;
     // distances of 64 and more go through LDS.
     if (a.order != nullptr) {

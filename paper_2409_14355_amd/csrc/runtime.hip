@@ -45,6 +45,7 @@ struct mpnl_ctx {
     size_t held = 0;
     int last_hip = 0;
     int precision = MPNL_PREC_FP32;
+    bool prune = true;  // stop path-search waves that can no longer win
     std::vector<Block> blocks;
     std::vector<mpnl_slot *> slots;
     std::vector<mpnl_batch *> batches;
@@ -315,7 +316,8 @@ size_t job_device_bytes(const mpnl_job &j)
     sd.N = j.N;
     sd.K = K;
     return align_up(L.total) + align_up((size_t)j.T * j.S * j.N * sizeof(float2)) +
-           align_up(path_partial_bytes(sd, j.T)) + align_up(sizeof(JobDev));
+           align_up((size_t)j.T * j.S * sizeof(float)) + align_up(path_partial_bytes(sd, j.T)) +
+           align_up(sizeof(JobDev));
 }
 
 }  // namespace mpnl
@@ -396,19 +398,17 @@ int detect_impl(mpnl_ctx *ctx, mpnl_slot *slot, const void *y, int T, int32_t *o
     const mpnl::SlotDev &sd = slot->sd;
     if ((long long)sd.S * T > INT_MAX / 2)
         return MPNL_E_UNSUPPORTED;
-    const size_t yt_bytes = (size_t)T * sd.S * sd.N * sizeof(float2);
-    const size_t part_bytes = soft ? 0 : mpnl::path_partial_bytes(sd, T);
+    const size_t yt_bytes = align_up((size_t)T * sd.S * sd.N * sizeof(float2));
+    const size_t part_bytes = align_up(soft ? 0 : mpnl::path_partial_bytes(sd, T));
+    const size_t bound_bytes = (!soft && ctx->prune) ? align_up((size_t)T * sd.S * sizeof(float)) : 0;
     int blk = -1;
-    int rc = pool_alloc(ctx, align_up(yt_bytes) + part_bytes, st, &blk);
+    int rc = pool_alloc(ctx, yt_bytes + part_bytes + bound_bytes, st, &blk);
     if (rc != MPNL_OK)
         return rc;
     char *base = (char *)ctx->blocks[blk].ptr;
     float2 *yt = (float2 *)base;
-    float *part = part_bytes ? (float *)(base + align_up(yt_bytes)) : nullptr;
-    if (part_bytes && align_up(yt_bytes) + part_bytes > ctx->blocks[blk].size) {
-        pool_release(ctx, blk, st);
-        return MPNL_E_NOMEM;
-    }
+    float *part = part_bytes ? (float *)(base + yt_bytes) : nullptr;
+    float *bound = bound_bytes ? (float *)(base + yt_bytes + part_bytes) : nullptr;
     hipError_t e;
     {
         StageTimer tm(ctx, MPNL_STAGE_ROTATE, st);
@@ -419,7 +419,7 @@ int detect_impl(mpnl_ctx *ctx, mpnl_slot *slot, const void *y, int T, int32_t *o
         if (soft)
             e = mpnl::launch_path_search_soft(sd, yt, T, sigma2, clip, llr, out, st);
         else
-            e = mpnl::launch_path_search(sd, yt, T, out, ctx->precision, part, st);
+            e = mpnl::launch_path_search(sd, yt, T, out, ctx->precision, part, bound, st);
     }
     pool_release(ctx, blk, st);
     slot->stream = st;
@@ -434,7 +434,7 @@ extern "C" {
 
 int mpnl_create(mpnl_ctx **ctx, int device, size_t hbm_budget_bytes, unsigned flags)
 {
-    if (!ctx || flags != 0)
+    if (!ctx || (flags & ~MPNL_CREATE_NO_PRUNE))
         return MPNL_E_INVAL;
     *ctx = nullptr;
     int n = 0;
@@ -445,6 +445,7 @@ int mpnl_create(mpnl_ctx **ctx, int device, size_t hbm_budget_bytes, unsigned fl
         return MPNL_E_NOMEM;
     c->device = device;
     c->budget = hbm_budget_bytes;
+    c->prune = (flags & MPNL_CREATE_NO_PRUNE) == 0;
     *ctx = c;
     return MPNL_OK;
 }
@@ -699,7 +700,9 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
             continue;
         }
         batched[i] = 1;
-        rc = pool_alloc(ctx, (size_t)j.T * j.S * j.N * sizeof(float2), st, &ytb[i]);
+        rc = pool_alloc(ctx, align_up((size_t)j.T * j.S * j.N * sizeof(float2)) +
+                                 (ctx->prune ? (size_t)j.T * j.S * sizeof(float) : 0),
+                        st, &ytb[i]);
         if (rc != MPNL_OK)
             break;
         hipError_t e;
@@ -776,15 +779,20 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
         if (rc == MPNL_OK && !groups.empty()) {
             char *host = (char *)sg->ptr;
             char *dev = (char *)ctx->blocks[tblk].ptr;
-            std::vector<int> items(groups.size()), threads(groups.size());
+            std::vector<int> items(groups.size()), threads(groups.size()), bitems(groups.size());
             for (size_t q = 0; q < groups.size(); ++q) {
                 mpnl::JobDev *jd = (mpnl::JobDev *)(host + goff[q]);
-                int acc = 0;
+                int acc = 0, bacc = 0;
                 for (size_t u = 0; u < groups[q].idx.size(); ++u) {
                     const int i = groups[q].idx[u];
                     const mpnl::SlotDev &sd = slots[i]->sd;
                     mpnl::JobDev &J = jd[u];
                     J.yt = (const float2 *)ctx->blocks[ytb[i]].ptr;
+                    J.bound = ctx->prune ? (float *)((char *)ctx->blocks[ytb[i]].ptr +
+                                                     align_up((size_t)jobs[i].T * sd.S * sd.N * sizeof(float2)))
+                                         : nullptr;
+                    J.bound_begin = bacc;
+                    bacc += sd.S * ((jobs[i].T + 63) / 64);
                     J.rlat = sd.rlat;
                     J.rq = rq_of(sd, ctx->precision);
                     J.diag = sd.diag;
@@ -801,6 +809,7 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
                     acc += sd.S * jobs[i].T;
                 }
                 items[q] = acc;
+                bitems[q] = bacc;
                 threads[q] = groups[q].threads;
             }
             hipError_t e = hipMemcpyAsync(dev, host, table_bytes, hipMemcpyHostToDevice, st);
@@ -810,7 +819,11 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
             for (size_t q = 0; q < groups.size() && e == hipSuccess; ++q) {
                 const mpnl::JobDev *jd = (const mpnl::JobDev *)(dev + goff[q]);
                 StageTimer tm(ctx, MPNL_STAGE_PATHS, st);
-                e = mpnl::launch_path_search_multi(jd, (int)groups[q].idx.size(), items[q], groups[q].N,
+                if (ctx->prune)
+                    e = mpnl::launch_path_bound_multi(jd, (int)groups[q].idx.size(), bitems[q], groups[q].N,
+                                                      groups[q].bits, ctx->precision, st);
+                if (e == hipSuccess)
+                    e = mpnl::launch_path_search_multi(jd, (int)groups[q].idx.size(), items[q], groups[q].N,
                                                    groups[q].bits, ctx->precision, threads[q], 1, st);
             }
             if (e != hipSuccess)
@@ -907,6 +920,7 @@ struct PlanLaunch {
     int threads;      // a4 workgroup size
     int nmax;         // a2: largest N (LDS size)
     int vpw;          // a4: received vectors per workgroup (tuned)
+    int bound_items;  // a4: items of the pruning-bound launch
     int items;
     size_t off;       // byte offset of the job table in a table buffer
     std::vector<int> jobs;
@@ -920,6 +934,7 @@ struct mpnl_batch {
     std::vector<mpnl_job> shapes;
     std::vector<mpnl::SlotDev> sd;
     std::vector<float2 *> yt;
+    std::vector<float *> bound;  // per job pruning bounds, or null
     std::vector<PlanLaunch> launches;
     int block = -1;
     size_t table_bytes = 0;
@@ -933,6 +948,7 @@ struct mpnl_batch {
     bool autotune = false;
     bool tuned = false;
     int precision = MPNL_PREC_FP32;
+    bool prune = true;
     hipStream_t cap = nullptr;
 };
 
@@ -946,12 +962,15 @@ void plan_fill(mpnl_batch *p, int b, const mpnl_job *jobs)
     for (const PlanLaunch &L : p->launches) {
         if (L.kind == L_PATHS) {
             mpnl::JobDev *jd = (mpnl::JobDev *)(host + L.off);
-            int acc = 0;
+            int acc = 0, bacc = 0;
             for (size_t u = 0; u < L.jobs.size(); ++u) {
                 const int i = L.jobs[u];
                 const mpnl::SlotDev &sd = p->sd[i];
                 mpnl::JobDev &J = jd[u];
                 J.yt = p->yt[i];
+                J.bound = p->bound[i];
+                J.bound_begin = bacc;
+                bacc += sd.S * ((jobs[i].T + 63) / 64);
                 J.rlat = sd.rlat;
                 J.rq = rq_of(sd, p->precision);
                 J.diag = sd.diag;
@@ -1010,8 +1029,12 @@ hipError_t plan_enqueue(mpnl_batch *p, int b, hipStream_t st, mpnl_ctx *timed = 
             e = mpnl::launch_rotate_batch((const mpnl::dev::StageJob *)tab, nj, L.items, st);
             break;
         default:
-            e = mpnl::launch_path_search_multi((const mpnl::JobDev *)tab, nj, L.items, L.param, L.bits, p->precision,
-                                               L.threads, L.vpw, st);
+            if (p->prune)
+                e = mpnl::launch_path_bound_multi((const mpnl::JobDev *)tab, nj, L.bound_items, L.param, L.bits,
+                                                  p->precision, st);
+            if (e == hipSuccess)
+                e = mpnl::launch_path_search_multi((const mpnl::JobDev *)tab, nj, L.items, L.param, L.bits,
+                                                   p->precision, L.threads, L.vpw, st);
         }
     }
     return e;
@@ -1143,10 +1166,11 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
     p->shapes.assign(shapes, shapes + n_jobs);
     p->autotune = (flags & MPNL_BATCH_AUTOTUNE) != 0;
     p->precision = ctx->precision;
+    p->prune = ctx->prune;
 
     // device memory: every job's slot state and rotated vectors
     std::vector<SlotLayout> lay(n_jobs);
-    std::vector<size_t> base(n_jobs), ytoff(n_jobs);
+    std::vector<size_t> base(n_jobs), ytoff(n_jobs), boff(n_jobs);
     size_t total = 0;
     for (int i = 0; i < n_jobs; ++i) {
         const mpnl_job &j = shapes[i];
@@ -1156,6 +1180,9 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
         total += lay[i].total;
         ytoff[i] = total;
         total += align_up((size_t)j.T * j.S * j.N * sizeof(float2));
+        boff[i] = total;
+        if (ctx->prune)
+            total += align_up((size_t)j.T * j.S * sizeof(float));
     }
     // launch groups
     auto group = [&](int kind, int param, int bits, int threads) -> PlanLaunch & {
@@ -1189,6 +1216,7 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
             } else {
                 L = &group(L_PATHS, j.N, j.mod, (K + 63) / 64 * 64);
                 L->items += j.S * j.T;
+                L->bound_items += j.S * ((j.T + 63) / 64);
             }
             L->jobs.push_back(i);
         }
@@ -1232,6 +1260,7 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
         sd.rec = nullptr;
         p->sd.push_back(sd);
         p->yt.push_back((float2 *)(dbase + ytoff[i]));
+        p->bound.push_back(ctx->prune ? (float *)(dbase + boff[i]) : nullptr);
     }
     hipError_t e = hipSuccess;
     for (int b = 0; b < kGraphCopies && e == hipSuccess; ++b) {

@@ -352,3 +352,41 @@ def test_soft_output_matches_oracle(ctx, snr, K, bits):
             if r["kth_margin"] < TOL:
                 continue
             assert np.allclose(llr[t, s], ol, rtol=1e-3, atol=2e-3 * max(1.0, np.abs(ol).max())), (t, s)
+
+
+@pytest.mark.parametrize("shape", [(400, 14, 16, 16, 4, 256, 16.0, "iid"), (300, 14, 24, 24, 4, 256, 18.0, "kron"),
+                                   (200, 14, 30, 28, 6, 128, 20.0, "iid"), (150, 14, 8, 8, 2, 300, 6.0, "iid"),
+                                   (300, 3, 12, 12, 4, 64, 10.0, "iid")])
+def test_pruning_changes_no_decision(mp, shape):
+    """Pruned search (waves stop once every path exceeds path 0's metric) and
+    the full search give identical symbols, in every precision and through
+    the batched and planned launches."""
+    S, T, M, N, bits, K, snr, ch = shape
+    _say("pruning", shape)
+    sl = synth.make_slot(S=S, T=T, M=M, N=N, bits=bits, snr_db=snr, seed=(230, S, N), channel=ch,
+                         rho_rx=0.5, rho_tx=0.3)
+    H, y = _dev(sl.H), _dev(sl.y)
+    full = mp.Context(0, prune=False)
+    pruned = mp.Context(0)
+    try:
+        for prec in (0, 1, 2):
+            full.set_precision(prec)
+            pruned.set_precision(prec)
+            a = full.detect(H, y, bits, K)
+            b = pruned.detect(H, y, bits, K)
+            c = pruned.detect_batch([dict(H=H, y=y, mod=bits, n_paths=K, out=None)])[0]
+            torch.cuda.synchronize()
+            assert torch.equal(a, b), prec
+            assert torch.equal(a, c), prec
+            if K <= 256:
+                plan = pruned.batch_plan([dict(S=S, T=T, M=M, N=N, mod=bits, n_paths=K)])
+                try:
+                    out = torch.full((T, S, N), -1, dtype=torch.int32, device="cuda:0")
+                    plan.run([dict(H=H, y=y, mod=bits, n_paths=K, out=out)])
+                    torch.cuda.synchronize()
+                    assert torch.equal(a, out), prec
+                finally:
+                    plan.close()
+    finally:
+        full.close()
+        pruned.close()
