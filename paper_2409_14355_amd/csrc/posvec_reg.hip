@@ -86,11 +86,14 @@ struct PosLds {
     uint32_t ap0;        // packed word of entry 0 of A
 };
 
-// LDS of one workgroup: PosLds, then N * KP back pointers (parent, k) per depth.
+// LDS of one workgroup: PosLds, then N * KP back pointers per depth, 16 bits
+// each (parent position | k << 8).  For 256 paths and N = 16 that is 24 KB,
+// so six workgroups fit a compute unit and a 1200-subcarrier slot runs in a
+// single round of workgroups.
 template <int E>
 constexpr size_t pos_lds_bytes(int N)
 {
-    return sizeof(PosLds<E>) + (size_t)N * 64 * E * sizeof(uint32_t);
+    return sizeof(PosLds<E>) + (size_t)N * 64 * E * sizeof(uint16_t);
 }
 
 template <int E>
@@ -99,7 +102,7 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
     constexpr int KP = 64 * E;
     constexpr double INF = (double)INFINITY;
     PosLds<E> &sh = *(PosLds<E> *)smem;
-    uint32_t *rec = (uint32_t *)(smem + sizeof(PosLds<E>));
+    uint16_t *rec = (uint16_t *)(smem + sizeof(PosLds<E>));
     const int g = (int)threadIdx.x;  // list entry of this lane
     const int lane = g & 63, wv = g >> 6;
     const int K = a.K, N = a.N, nq = a.nq;
@@ -222,7 +225,7 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
         if (Zs < INF) {
             const uint32_t k = (Zp >> 12) & 63;
             const uint32_t lx = sh.run[Zp >> 18] + k;
-            rec[(size_t)d * KP + g] = (Zp & 0xfff) | (k << 16);
+            rec[(size_t)d * KP + g] = (uint16_t)((Zp & 0xffu) | (k << 8));  // parent position < 256
             As = Zs;
             Ap = (uint32_t)g | (lx << 18);
         } else {
@@ -250,8 +253,8 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
         int pidx = r;
         for (int d = N - 1; d >= 0; --d) {
             const uint32_t e = rec[(size_t)d * KP + pidx];
-            const uint32_t pk = (e >> 16) + 1u;
-            pidx = (int)(e & 0xffffu);
+            const uint32_t pk = (e >> 8) + 1u;
+            pidx = (int)(e & 0xffu);
             m3 |= (pk >= 3u ? 1u : 0u) << d;
             m2 |= (pk >= 2u ? 1u : 0u) << d;
 #pragma unroll
