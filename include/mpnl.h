@@ -123,7 +123,8 @@ int mpnl_memory_usage(const mpnl_ctx *ctx, size_t *held, size_t *in_use);
 #define MPNL_STAGE_POSVEC 1      /* a2 position-vector set                     */
 #define MPNL_STAGE_ROTATE 2      /* a3 yt = Q^H y                              */
 #define MPNL_STAGE_PATHS 3       /* a4 + a5 path search and minimum            */
-#define MPNL_NUM_STAGES 4
+#define MPNL_STAGE_BOUND 4       /* path 0's metric per vector (pruning bound) */
+#define MPNL_NUM_STAGES 5
 
 /* Enable (1) or disable (0) kernel timers: while enabled every kernel launch
    of the context is bracketed by two HIP events recorded on its stream.

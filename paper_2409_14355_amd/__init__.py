@@ -42,8 +42,8 @@ EXPORTED = (
 MPNL_JOB_DONE, MPNL_JOB_REJECTED, MPNL_JOB_DROPPED, MPNL_JOB_FAILED = 0, 1, 2, 3
 MPNL_CREATE_NO_PRUNE = 1
 MPNL_BATCH_AUTOTUNE = 1
-MPNL_STAGE_SQRD, MPNL_STAGE_POSVEC, MPNL_STAGE_ROTATE, MPNL_STAGE_PATHS = 0, 1, 2, 3
-STAGE_NAMES = ("sqrd", "posvec", "rotate", "paths")
+MPNL_STAGE_SQRD, MPNL_STAGE_POSVEC, MPNL_STAGE_ROTATE, MPNL_STAGE_PATHS, MPNL_STAGE_BOUND = 0, 1, 2, 3, 4
+STAGE_NAMES = ("sqrd", "posvec", "rotate", "paths", "bound")
 
 
 class mpnl_server_config(ctypes.Structure):
@@ -305,10 +305,11 @@ def mpnl_profile_enable(ctx: int, enable: bool) -> None:
 
 def mpnl_profile_collect(ctx: int) -> dict:
     """-> {stage name: (total milliseconds, launches)} since the last collect."""
-    ms = (ctypes.c_double * 4)()
-    n = (ctypes.c_int * 4)()
+    ns = len(STAGE_NAMES)
+    ms = (ctypes.c_double * ns)()
+    n = (ctypes.c_int * ns)()
     _check(lib().mpnl_profile_collect(ctx, ms, n), "mpnl_profile_collect")
-    return {STAGE_NAMES[i]: (ms[i], n[i]) for i in range(4)}
+    return {STAGE_NAMES[i]: (ms[i], n[i]) for i in range(ns)}
 
 
 # ---- convenience layer ------------------------------------------------------------

@@ -330,12 +330,7 @@ hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_
         return hipErrorInvalidValue;
     PathArgs a = path_args(sd, yt, T, out);
     a.rq = precision == PREC_FP16 ? sd.rlat_h : precision == PREC_BF16 ? sd.rlat_b : nullptr;
-    if (bound != nullptr) {
-        a.bound = bound;
-        const hipError_t eb = kBoundLaunch[sd.N - 1](a, sd.bits, precision, st);
-        if (eb != hipSuccess)
-            return eb;
-    }
+    a.bound = bound;
     const int groups = (sd.K + 255) / 256;
     if (groups > 1) {
         if (part == nullptr)
@@ -369,6 +364,17 @@ hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, f
     case 24: return soft_launch_nmax24(a, sd.bits, st);
     default: return soft_launch_nmax32(a, sd.bits, st);
     }
+}
+
+hipError_t launch_path_bound(const SlotDev &sd, const float2 *yt, int T, int precision, float *bound,
+                             hipStream_t st)
+{
+    if (sd.N < 1 || sd.N > 32 || bound == nullptr)
+        return hipErrorInvalidValue;
+    PathArgs a = path_args(sd, yt, T, nullptr);
+    a.rq = precision == PREC_FP16 ? sd.rlat_h : precision == PREC_BF16 ? sd.rlat_b : nullptr;
+    a.bound = bound;
+    return kBoundLaunch[sd.N - 1](a, sd.bits, precision, st);
 }
 
 hipError_t launch_path_bound_multi(const JobDev *jobs_dev, int n_jobs, int bound_items, int N, int bits,

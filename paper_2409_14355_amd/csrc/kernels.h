@@ -51,6 +51,10 @@ hipError_t launch_rotate(const SlotDev &sd, const float2 *y, int T, float2 *yt, 
 size_t path_partial_bytes(const SlotDev &sd, int T);
 hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_t *out,
                               int precision, float *part, float *bound, hipStream_t st);
+// Pruning bounds (path 0's metric of every vector, (T, S)) for
+// launch_path_search; run before it on the same stream.
+hipError_t launch_path_bound(const SlotDev &sd, const float2 *yt, int T, int precision, float *bound,
+                             hipStream_t st);
 hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, float sigma2,
                                    float clip, float *llr, int32_t *out, hipStream_t st);
 // Batched path search over many jobs sharing (NMAX bucket, bits); one persistent launch.

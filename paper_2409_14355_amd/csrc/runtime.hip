@@ -46,6 +46,10 @@ struct mpnl_ctx {
     int last_hip = 0;
     int precision = MPNL_PREC_FP32;
     bool prune = true;  // stop path-search waves that can no longer win
+    // second stream of one-shot detection: the rotation and the pruning
+    // bounds run there while the position set runs on the caller's stream
+    hipStream_t aux = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     std::vector<Block> blocks;
     std::vector<mpnl_slot *> slots;
     std::vector<mpnl_batch *> batches;
@@ -325,7 +329,7 @@ size_t job_device_bytes(const mpnl_job &j)
 namespace {
 
 int prepare_impl(mpnl_ctx *ctx, const void *H, int S, int M, int N, int mod, int n_paths,
-                 hipStream_t st, mpnl_slot **out)
+                 hipStream_t st, mpnl_slot **out, bool run_posvec = true)
 {
     const int K = (int)std::min<long long>(n_paths, num_vectors_sat(1 << mod, N));
     const int NP = (N + 3) / 4 * 4;
@@ -366,7 +370,7 @@ int prepare_impl(mpnl_ctx *ctx, const void *H, int S, int M, int N, int mod, int
         StageTimer tm(ctx, MPNL_STAGE_SQRD, st);
         e = mpnl::launch_sqrd((const float2 *)H, sd, st);
     }
-    if (e == hipSuccess) {
+    if (e == hipSuccess && run_posvec) {
         StageTimer tm(ctx, MPNL_STAGE_POSVEC, st);
         e = mpnl::launch_posvec(sd, st);
     }
@@ -414,6 +418,10 @@ int detect_impl(mpnl_ctx *ctx, mpnl_slot *slot, const void *y, int T, int32_t *o
         StageTimer tm(ctx, MPNL_STAGE_ROTATE, st);
         e = mpnl::launch_rotate(sd, (const float2 *)y, T, yt, st);
     }
+    if (e == hipSuccess && bound) {
+        StageTimer tm(ctx, MPNL_STAGE_BOUND, st);
+        e = mpnl::launch_path_bound(sd, yt, T, ctx->precision, bound, st);
+    }
     if (e == hipSuccess) {
         StageTimer tm(ctx, MPNL_STAGE_PATHS, st);
         if (soft)
@@ -426,6 +434,71 @@ int detect_impl(mpnl_ctx *ctx, mpnl_slot *slot, const void *y, int T, int32_t *o
     if (e != hipSuccess)
         return hip_fail(ctx, e);
     return MPNL_OK;
+}
+
+// One-shot a1..a5 with the independent stages overlapped: after the sorted
+// QR, the rotation and the pruning bounds run on the context's second
+// stream while the position set runs on `st`; the path search waits for
+// both.  Everything is ordered after earlier work on `st`, and later work on
+// `st` is ordered after it.
+int oneshot_impl(mpnl_ctx *ctx, const void *H, const void *y, int S, int T, int M, int N, int mod, int n_paths,
+                 int32_t *out, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    if (!ctx->aux) {
+        e = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e);
+    }
+    mpnl_slot *slot = nullptr;
+    int rc = prepare_impl(ctx, H, S, M, N, mod, n_paths, st, &slot, false);
+    if (rc != MPNL_OK)
+        return rc;
+    const mpnl::SlotDev &sd = slot->sd;
+    const size_t yt_bytes = align_up((size_t)T * S * N * sizeof(float2));
+    const size_t part_bytes = align_up(mpnl::path_partial_bytes(sd, T));
+    const size_t bound_bytes = ctx->prune ? align_up((size_t)T * S * sizeof(float)) : 0;
+    int blk = -1;
+    rc = pool_alloc(ctx, yt_bytes + part_bytes + bound_bytes, st, &blk);
+    if (rc != MPNL_OK) {
+        release_impl(ctx, slot);
+        return rc;
+    }
+    char *base = (char *)ctx->blocks[blk].ptr;
+    float2 *yt = (float2 *)base;
+    float *part = part_bytes ? (float *)(base + yt_bytes) : nullptr;
+    float *bound = bound_bytes ? (float *)(base + yt_bytes + part_bytes) : nullptr;
+    e = hipEventRecord(ctx->fork_ev, st);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0);
+    if (e == hipSuccess) {
+        StageTimer tm(ctx, MPNL_STAGE_ROTATE, ctx->aux);
+        e = mpnl::launch_rotate(sd, (const float2 *)y, T, yt, ctx->aux);
+    }
+    if (e == hipSuccess && bound) {
+        StageTimer tm(ctx, MPNL_STAGE_BOUND, ctx->aux);
+        e = mpnl::launch_path_bound(sd, yt, T, ctx->precision, bound, ctx->aux);
+    }
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->join_ev, ctx->aux);
+    if (e == hipSuccess) {
+        StageTimer tm(ctx, MPNL_STAGE_POSVEC, st);
+        e = mpnl::launch_posvec(sd, st);
+    }
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(st, ctx->join_ev, 0);
+    if (e == hipSuccess) {
+        StageTimer tm(ctx, MPNL_STAGE_PATHS, st);
+        e = mpnl::launch_path_search(sd, yt, T, out, ctx->precision, part, bound, st);
+    }
+    pool_release(ctx, blk, st);
+    slot->stream = st;
+    release_impl(ctx, slot);
+    return e == hipSuccess ? MPNL_OK : hip_fail(ctx, e);
 }
 
 }  // namespace
@@ -472,6 +545,12 @@ int mpnl_destroy(mpnl_ctx *ctx)
         if (sg.ev)
             (void)hipEventDestroy(sg.ev);
     }
+    if (ctx->aux)
+        (void)hipStreamDestroy(ctx->aux);
+    if (ctx->fork_ev)
+        (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev)
+        (void)hipEventDestroy(ctx->join_ev);
     for (auto &t : ctx->timed) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
@@ -517,8 +596,8 @@ int mpnl_profile_collect(mpnl_ctx *ctx, double *total_ms, int *launches)
     if (!ctx)
         return MPNL_E_INVAL;
     DeviceGuard g(ctx->device);
-    double ms[MPNL_NUM_STAGES] = {0, 0, 0, 0};
-    int cnt[MPNL_NUM_STAGES] = {0, 0, 0, 0};
+    double ms[MPNL_NUM_STAGES] = {};
+    int cnt[MPNL_NUM_STAGES] = {};
     hipError_t err = hipSuccess;
     for (auto &t : ctx->timed) {
         float x = 0.f;
@@ -656,14 +735,7 @@ int mpnl_detect(mpnl_ctx *ctx, const void *H, const void *y, int S, int T, int M
     DeviceGuard g(ctx->device);
     if (!g.ok())
         return hip_fail(ctx, hipErrorInvalidDevice);
-    hipStream_t st = (hipStream_t)stream;
-    mpnl_slot *slot = nullptr;
-    rc = prepare_impl(ctx, H, S, M, N, mod, n_paths, st, &slot);
-    if (rc != MPNL_OK)
-        return rc;
-    rc = detect_impl(ctx, slot, y, T, out, st, false, 0.f, 0.f, nullptr);
-    release_impl(ctx, slot);
-    return rc;
+    return oneshot_impl(ctx, H, y, S, T, M, N, mod, n_paths, out, (hipStream_t)stream);
 }
 
 int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *stream)
@@ -818,10 +890,12 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
             sg->pending = e == hipSuccess;
             for (size_t q = 0; q < groups.size() && e == hipSuccess; ++q) {
                 const mpnl::JobDev *jd = (const mpnl::JobDev *)(dev + goff[q]);
-                StageTimer tm(ctx, MPNL_STAGE_PATHS, st);
-                if (ctx->prune)
+                if (ctx->prune) {
+                    StageTimer tb(ctx, MPNL_STAGE_BOUND, st);
                     e = mpnl::launch_path_bound_multi(jd, (int)groups[q].idx.size(), bitems[q], groups[q].N,
                                                       groups[q].bits, ctx->precision, st);
+                }
+                StageTimer tm(ctx, MPNL_STAGE_PATHS, st);
                 if (e == hipSuccess)
                     e = mpnl::launch_path_search_multi(jd, (int)groups[q].idx.size(), items[q], groups[q].N,
                                                    groups[q].bits, ctx->precision, threads[q], 1, st);
@@ -1029,9 +1103,11 @@ hipError_t plan_enqueue(mpnl_batch *p, int b, hipStream_t st, mpnl_ctx *timed = 
             e = mpnl::launch_rotate_batch((const mpnl::dev::StageJob *)tab, nj, L.items, st);
             break;
         default:
-            if (p->prune)
+            if (p->prune) {
+                StageTimer tb(timed ? timed : &off, MPNL_STAGE_BOUND, st);
                 e = mpnl::launch_path_bound_multi((const mpnl::JobDev *)tab, nj, L.bound_items, L.param, L.bits,
                                                   p->precision, st);
+            }
             if (e == hipSuccess)
                 e = mpnl::launch_path_search_multi((const mpnl::JobDev *)tab, nj, L.items, L.param, L.bits,
                                                    p->precision, L.threads, L.vpw, st);
