@@ -48,6 +48,31 @@ SWEEP_WORKLOAD = "16x16-qam16-S1200-T14-snr-sweep"
 ANTENNA_WORKLOAD = "antenna-search-qam16-20dB"
 
 
+def measured_traffic(workload: str, K: int, precision: str):
+    """HBM bytes per path-search launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated), only while the kernel's sources are
+    unchanged since the counters were taken; else None."""
+    import hashlib
+    if workload != "16x16-qam16-S1200-T14" or K != 256 or precision != "fp32":
+        return None
+    path = os.path.join(ROOT, "profiles", "traffic_path_search_16x16-qam16-S1200-T14-Np256.txt")
+    try:
+        kv = {}
+        for line in open(path):
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for f in kv["sources"].split():
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != kv["sources_sha256"]:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def path_flops_per_vector(N: int, K: int) -> int:
     """Algorithmic flops of the path search per received vector: for each of
     the K paths and each depth d, d complex multiply-subtracts (8 flops) plus
@@ -194,7 +219,7 @@ def main() -> int:
         "stage_ms_per_launch": stages,
         "roofline": {"bound": "alu", "kernel": "path_search_kernel", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": None,
+                     "traffic": measured_traffic(args.workload, Kc, args.precision),
                      "flops_per_launch": flops_launch, "avg_launch_ms": avg_paths_s * 1e3},
     }
     if not args.no_cpu_baseline:
