@@ -121,10 +121,18 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
         uint32_t Zp = Ap;
         const double a0s = sh.scA[0];
         const uint32_t a0p = sh.ap0;
+        // The first depth extends the root only: its children k = 0 .. |Q|-1
+        // are already in key order (scores non-decreasing in k, equal scores
+        // ordered by k), so entry g is child g and no merge is needed.
+        if (d == 0) {
+            const bool in = g < min(nq, K);
+            Zs = in ? cand_score_r(a0s, w, g) : INF;
+            Zp = in ? ((uint32_t)g << 12) : kSentinel;
+        }
         // Z covers the ranks k < span of this depth; merging Z with its copy
         // raised by span covers k < 2 span (|Q| is a power of two, so the
         // raised ranks never pass |Q| - 1)
-        for (int span = 1; span < nq; span <<= 1) {
+        for (int span = d == 0 ? nq : 1; span < nq; span <<= 1) {
             const bool ok = Zs < INF;
             const int par = Zp & 0xfff;
             const int k1 = ((Zp >> 12) & 63) + span;
