@@ -91,7 +91,7 @@ def cpu_baseline(sl, bits: int, K: int, n_sub: int) -> dict:
     # repeat the sample until about 10 s of wall time (at most 30 s)
     reps, dt = 0, 0.0
     t0 = time.perf_counter()
-    while dt < 10.0 and reps < 1000:
+    while dt < 10.0 and reps < 1000000:
         oracle.detect_slot("mpnl", sub.H, sub.y, bits, n_paths=K, nthreads=cores)
         reps += 1
         dt = time.perf_counter() - t0
@@ -232,6 +232,18 @@ def main() -> int:
     if not args.no_cpu_baseline:
         n_sub = args.cpu_subcarriers or min(S, {4: 64, 16: 1200, 24: 1000}.get(N, 200))
         res["cpu_baseline"] = cpu_baseline(sl, bits, Kc, n_sub)
+    if (1 << bits) ** N <= 4096 and not args.no_cpu_baseline:
+        # small systems: the exhaustive ML detector on the host (the
+        # configuration's comparison), its time and the GPU's agreement with it
+        import oracle
+        t0 = time.perf_counter()
+        ml = oracle.detect_slot("ml", sl.H, sl.y, bits, nthreads=os.cpu_count() or 1)
+        dt = time.perf_counter() - t0
+        got = out.cpu().numpy()
+        res["vs_exhaustive_ml"] = {
+            "candidates_per_vector": (1 << bits) ** N, "ml_host_s": dt,
+            "vector_agreement": float(np.mean(np.all(got == ml, axis=2))),
+            "ber_gpu": ber, "ber_ml": synth.bit_errors(ml, sl.s_idx, bits) / (sl.s_idx.size * bits)}
     if args.precision != "fp32":
         # decisions against the FP64 oracle on the first subcarriers, and the
         # BER of both on that sample
