@@ -18,8 +18,8 @@
 // lane gathers its column l, l + 64, ... and runs those stages in registers),
 // the stages inside a wavefront use DPP / row-swap lane exchanges.  An entry
 // is (score, packed) with packed = parent position (12 bits) | k (6 bits)
-// << 12 | lexical rank of the parent (12 bits) << 18, so the key
-// (score, parent rank, k) compares as (score, packed >> 12).
+// << 12 | lexical rank of the parent (14 bits) << 18, so the key
+// (score, parent rank, k) compares as (score, packed).
 #include "device_common.h"
 
 namespace mpnl {
@@ -28,15 +28,20 @@ namespace {
 
 constexpr uint32_t kSentinel = 0xffffffffu;
 
-// Branch-free (a short-circuit form compiles to divergent branches).
+// (score, packed) order.  Branch-free (a short-circuit form compiles to
+// divergent branches).  The whole packed word is compared: its low 12 bits
+// (parent position) only matter between words with equal (parent rank, k),
+// which no two distinct entries of one list share.
 __device__ __forceinline__ bool key_lt(double as, uint32_t ap, double bs, uint32_t bp)
 {
-    return (as < bs) | ((as == bs) & ((ap >> 12) < (bp >> 12)));
+    return (as < bs) | ((as == bs) & (ap < bp));
 }
 
+// parent + w k, product and sum rounded separately (no fused multiply-add)
 __device__ __forceinline__ double cand_score_r(double parent, double w, int k)
 {
-    return __dadd_rn(parent, __dmul_rn(w, (double)k));
+#pragma clang fp contract(off)
+    return parent + w * (double)k;
 }
 
 // Compare-exchange of entry (cs, cp) with the entry of lane ^ s, keeping the
@@ -51,24 +56,23 @@ __device__ __forceinline__ void lane_stage(double &cs, uint32_t &cp, int s, bool
     cp = take ? op : cp;
 }
 
-// Register stages js = E/2 .. 1 (entry distance 64 js) of an ascending
-// bitonic merge over a column of E entries.
+// Entry `pos` of the column of E entries after the register stages
+// js = E/2 .. 1 (entry distance 64 js) of an ascending bitonic merge.  The
+// entry at pos is the min or the max (bit js of pos) of a pair at every stage,
+// so only the E - 1 pairs on its way are compared.  `pos` is the same in
+// every lane of the wavefront.
 template <int E>
-__device__ __forceinline__ void column_finish(double (&cs)[E], uint32_t (&cp)[E])
+__device__ __forceinline__ void column_pick(double (&cs)[E], uint32_t (&cp)[E], int pos)
 {
 #pragma unroll
     for (int js = E / 2; js >= 1; js >>= 1) {
+        const bool want_max = (pos & js) != 0;
 #pragma unroll
-        for (int j = 0; j < E; ++j)
-            if ((j & js) == 0) {
-                const double ls = cs[j], hs = cs[j + js];
-                const uint32_t lp = cp[j], hp = cp[j + js];
-                const bool sw = key_lt(hs, hp, ls, lp);
-                cs[j] = sw ? hs : ls;
-                cp[j] = sw ? hp : lp;
-                cs[j + js] = sw ? ls : hs;
-                cp[j + js] = sw ? lp : hp;
-            }
+        for (int j = 0; j < js; ++j) {
+            const bool take_hi = key_lt(cs[j + js], cp[j + js], cs[j], cp[j]) != want_max;
+            cs[j] = take_hi ? cs[j + js] : cs[j];
+            cp[j] = take_hi ? cp[j + js] : cp[j];
+        }
     }
 }
 
@@ -184,16 +188,11 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
                     cs[j] = tb ? rs : zs;
                     cp[j] = tb ? rp : zp;
                 }
-                column_finish<E>(cs, cp);
+                column_pick<E>(cs, cp, wv);
                 buf ^= 1;
             }
             Zs = cs[0];
             Zp = cp[0];
-#pragma unroll
-            for (int j = 1; j < E; ++j) {
-                Zs = j == wv ? cs[j] : Zs;
-                Zp = j == wv ? cp[j] : Zp;
-            }
 #pragma unroll
             for (int st = 32; st >= 1; st >>= 1)
                 lane_stage(Zs, Zp, st, true);

@@ -256,9 +256,12 @@ __device__ __forceinline__ bool key_less(double sa, int la, int ka, double sb, i
     return sa < sb || (sa == sb && (la < lb || (la == lb && ka < kb)));
 }
 
+// parent + w k with the product and the sum rounded separately (no fused
+// multiply-add), the rounding of a score summed term by term in depth order
 __device__ __forceinline__ double cand_score(double parent, double w, int k)
 {
-    return __dadd_rn(parent, __dmul_rn(w, (double)k));
+#pragma clang fp contract(off)
+    return parent + w * (double)k;
 }
 
 template <bool REC_LDS>
