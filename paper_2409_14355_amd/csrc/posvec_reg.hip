@@ -76,6 +76,20 @@ __device__ __forceinline__ void column_pick(double (&cs)[E], uint32_t (&cp)[E], 
     }
 }
 
+// Inclusive prefix sum over the 64 lanes: four row shifts inside each row of
+// 16, then row 0's total into row 1 and row 2's into row 3 (row_bcast:15),
+// then the total of rows 0-1 into rows 2-3 (row_bcast:31).
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false); // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false); // row_bcast:31
+    return v;
+}
+
 template <int E>
 struct PosLds {
     static constexpr int KP = 64 * E;
@@ -85,8 +99,8 @@ struct PosLds {
     double bcs[2];       // broadcast of entry K-1 of Z
     uint32_t bcp[2];
     uint32_t cnt[KP];    // children per parent lexical rank
-    uint32_t run[KP];    // exclusive prefix of cnt
-    uint32_t wsum[E];
+    uint32_t run[KP];    // exclusive prefix of cnt inside each wavefront
+    uint32_t wsum[E];    // cnt total of each wavefront
     uint32_t ap0;        // packed word of entry 0 of A
 };
 
@@ -114,6 +128,7 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
     double As = g == 0 ? 0.0 : INF;
     uint32_t Ap = g == 0 ? 0u : kSentinel;
     sh.scA[g] = As;
+    sh.cnt[g] = 0;
     if (g == 0)
         sh.ap0 = 0u;
     __syncthreads();
@@ -202,36 +217,28 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
             }
         }
         // lexical ranks of the new prefixes: the children of a parent are
-        // k = 0..c-1, consecutive in lexical order
-        sh.cnt[g] = 0;
-        __syncthreads();
+        // k = 0..c-1, consecutive in lexical order.  cnt[] is zero here (set
+        // at the start and cleared by its reader below).
         if (Zs < INF)
             atomicMax(&sh.cnt[Zp >> 18], ((Zp >> 12) & 63) + 1);
         __syncthreads();
         {
             const uint32_t v = sh.cnt[g];
-            uint32_t incl = v;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t t = __shfl_up(incl, off);
-                if (lane >= off)
-                    incl += t;
-            }
-            uint32_t base = 0;
-            if constexpr (E > 1) {
-                if (lane == 63)
-                    sh.wsum[wv] = incl;
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < E - 1; ++j)
-                    base += j < wv ? sh.wsum[j] : 0u;
-            }
-            sh.run[g] = base + incl - v;
+            sh.cnt[g] = 0;
+            const uint32_t incl = wave_scan_incl(v);
+            if (E > 1 && lane == 63)
+                sh.wsum[wv] = incl;
+            sh.run[g] = incl - v;  // exclusive prefix inside the wavefront
         }
         __syncthreads();
         if (Zs < INF) {
             const uint32_t k = (Zp >> 12) & 63;
-            const uint32_t lx = sh.run[Zp >> 18] + k;
+            const uint32_t pr = Zp >> 18;  // parent's lexical rank
+            uint32_t base = 0;
+#pragma unroll
+            for (int j = 0; j < E - 1; ++j)
+                base += (uint32_t)j < (pr >> 6) ? sh.wsum[j] : 0u;
+            const uint32_t lx = sh.run[pr] + base + k;
             rec[(size_t)d * KP + g] = (uint16_t)((Zp & 0xffu) | (k << 8));  // parent position < 256
             As = Zs;
             Ap = (uint32_t)g | (lx << 18);
