@@ -356,12 +356,24 @@ __device__ __forceinline__ constexpr float code_weight(int d)
 // Pruning.  The accumulated metric never decreases along a path, so a path
 // whose partial metric already exceeds the metric of some complete path can
 // no longer be the minimum.  Path 0 (the first choice at every depth) is
-// evaluated per received vector before the search (path_bound_kernel); a
-// wavefront whose paths all exceed that bound, padded by kBoundPad for
-// rounding differences between the two evaluations, stops descending.  The
-// winner and its tie rule are unchanged: every pruned path has a metric
-// strictly above the minimum.
+// evaluated per received vector before the search (path_bound_kernel), which
+// leaves a record per vector: the metric of path 0, then its packed decisions.
+// In the search, a wavefront whose paths all exceed that bound (padded by
+// kBoundPad) stops descending, and the lane of path 0 takes its metric and
+// decisions from the record, so it holds no wavefront up.  Both evaluations
+// of path 0 run the same arithmetic in the same order, so its metric is the
+// same bits either way.  The winner and its tie rule are unchanged: every
+// pruned path has a metric strictly above the minimum.
 constexpr float kBoundPad = 1.0001f;
+
+// x * x rounded on its own: never fused into the sum that follows, so the
+// first-choice distances (all of path 0's metric) round alike in every
+// instantiation of the descent, whatever branches surround them.
+__device__ __forceinline__ float square_rn(float x)
+{
+#pragma clang fp contract(off)
+    return x * x;
+}
 
 // One SIC descent from the residuals b (yt of the vector) driven by the
 // position vector in pw.  After each decision the residuals of the depths
@@ -384,13 +396,13 @@ __device__ __forceinline__ float descend(float2 (&b)[N], cptr<float> dg, cptr<fl
             const int idx = min(max(k - 1, 0), L * L - 1);
             mI = (float)gray_decode(idx >> Axis<L>::HB);
             mQ = (float)gray_decode(idx & (L - 1));
-            eI = zI * zI;
-            eQ = zQ * zQ;
+            eI = square_rn(zI);
+            eQ = square_rn(zQ);
         } else {
             const float lI = nearest_level<L>(zI, mI), lQ = nearest_level<L>(zQ, mQ);
             const float dI = zI - lI, dQ = zQ - lQ;
-            eI = dI * dI;
-            eQ = dQ * dQ;
+            eI = square_rn(dI);
+            eQ = square_rn(dQ);
             if (FIRST) {
             } else if (k == 2) {
                 // rank 2 is (second I, closest Q) or (closest I, second Q):
@@ -509,13 +521,17 @@ __device__ __forceinline__ int block_argmin(float bm, int br, int W, float *sm, 
 // leaves its best (metric, path, decisions) for path_group_reduce_kernel.
 // Every lane of the workgroup calls this (it may synchronise the workgroup);
 // lanes of an inactive vector do no work.
+// b0 / b0d: path 0's metric and packed decisions from the pruning record
+// (b0d null: no record, path 0 is searched like the others).
 template <int N, int L, int PREC>
 __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cptr<float> rl,
                                               cptr<uint32_t> rq, const uint8_t *Pbase,
                                               const uint16_t *order, int K, int NP, int group,
                                               const int32_t *pm, int32_t *o, float *part, float *sm,
-                                              int *sr, int W, int tid, bool active, float prune)
+                                              int *sr, int W, int tid, bool active, float b0,
+                                              const float *b0d)
 {
+    const float prune = b0 * kBoundPad;
     constexpr int NW = (N + 3) / 4;
     const uint32_t *Pw = (const uint32_t *)Pbase;
     const int nw = NP >> 2;
@@ -539,10 +555,16 @@ __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cp
 #pragma unroll
         for (int d = 0; d < N; ++d)
             b[d] = ld2(yv, d);
-        const float m = descend<N, L, PREC>(b, dg, rl, rq, pw, decf, prune, valid);
+        const bool known = valid && r == 0 && b0d != nullptr;
+        const float m = descend<N, L, PREC>(b, dg, rl, rq, pw, decf, prune, valid && !known);
         if (valid) {
-            bm = m;
+            bm = known ? b0 : m;
             br = r;
+        }
+        if (known) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+                decf[w] = b0d[w];
         }
     }
     const int gr = block_argmin(bm, br, W, sm, sr);
@@ -576,11 +598,12 @@ __global__ __launch_bounds__(256) void path_search_kernel(PathArgs a)
     const size_t v = (size_t)t * a.S + s;
     cptr<uint32_t> rq = a.rq ? uniform_ptr(a.rq + sN * N) : nullptr;
     float *part = a.part ? a.part + (v * gridDim.y + blockIdx.y) * (2 + (N + 3) / 4) : nullptr;
-    const float prune = a.bound ? uniform_ptr(a.bound + v)[0] * kBoundPad : INFINITY;
+    const float b0 = a.bound ? uniform_ptr(a.bound + v)[0] : INFINITY;
+    const float *b0d = a.bound ? a.bound + (size_t)a.S * a.T + v * ((N + 3) / 4) : nullptr;
     search_vector<N, L, PREC>(uniform_ptr(a.yt + v * N), uniform_ptr(a.diag + sN), uniform_ptr(a.rlat + sN * N),
                               rq, a.P + (size_t)s * a.K * a.NP, a.order ? a.order + (size_t)s * a.K : nullptr,
                               a.K, a.NP, blockIdx.y, a.permd + sN, a.out + v * N, part, sm, sr, (int)blockDim.x,
-                              (int)threadIdx.x, true, prune);
+                              (int)threadIdx.x, true, b0, b0d);
 }
 
 // Best of the path groups of every received vector (equal metrics: lowest
@@ -748,16 +771,18 @@ __global__ __launch_bounds__(256) void path_search_multi_kernel(MultiArgs a)
     const size_t sN = (size_t)s * N;
     const size_t v = (size_t)t * j.S + s;
     cptr<uint32_t> rq = j.rq ? uniform_ptr(j.rq + sN * N) : nullptr;
-    const float prune = j.bound ? uniform_ptr(j.bound + v)[0] * kBoundPad : INFINITY;
+    const float b0 = j.bound ? uniform_ptr(j.bound + v)[0] : INFINITY;
+    const float *b0d = j.bound ? j.bound + (size_t)j.S * j.T + v * ((N + 3) / 4) : nullptr;
     search_vector<N, L, PREC>(uniform_ptr(j.yt + v * N), uniform_ptr(j.diag + sN), uniform_ptr(j.rlat + sN * N), rq,
                               j.P + (size_t)s * j.K * j.NP, j.order ? j.order + (size_t)s * j.K : nullptr, j.K,
                               j.NP, 0, j.permd + sN, j.out + v * N, nullptr, sm, sr, W, (int)threadIdx.x - q * W,
-                              active, prune);
+                              active, b0, b0d);
 }
 
 // ============================================================================
-// Pruning bound: the metric of path 0 (first choice at every depth) of every
-// received vector, computed with the same descent as the path search.  A
+// Pruning record: path 0 (first choice at every depth) of every received
+// vector, computed with the same descent as the path search; the metrics,
+// (T, S) floats, then the packed decisions, (T, S, (N + 3) / 4) floats.  A
 // wavefront per (subcarrier, 64 symbols); lane t runs symbol t0 + t (lanes
 // past the last symbol repeat it and write nothing).
 // ============================================================================
@@ -781,8 +806,14 @@ __device__ __forceinline__ void bound_body(const float2 *yt, cptr<float> dg, cpt
         decf[w] = 0.f;
     }
     const float m = descend<N, L, PREC, true>(b, dg, rl, rq, pw, decf, INFINITY, true);
-    if (t < T)
-        bound[(size_t)t * S + s] = m;
+    if (t < T) {
+        const size_t v = (size_t)t * S + s;
+        bound[v] = m;
+        float *dec = bound + (size_t)S * T + v * NW;
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+            dec[w] = decf[w];
+    }
 }
 
 // grid: S * ceil(T / 64) wavefronts

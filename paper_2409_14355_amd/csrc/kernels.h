@@ -35,11 +35,18 @@ struct JobDev {
     const uint8_t *P;
     const uint16_t *order;
     int32_t *out;          // (T, S, N)
-    float *bound;          // (T, S) pruning bound per vector (path 0's metric), or null
+    float *bound;          // pruning record (bound_record_bytes), or null
     int S, T, N, K, NP;
     int item_begin;        // first global work item of this job
     int bound_begin;       // first item of this job in the bound launch (S * ceil(T / 64) items a job)
 };
+
+// Pruning record of a (S, T) job with N users: path 0's metric per vector,
+// (T, S) floats, then its packed decisions, (T, S, (N + 3) / 4) floats.
+inline size_t bound_record_bytes(int S, int T, int N)
+{
+    return (size_t)S * T * (1 + (N + 3) / 4) * sizeof(float);
+}
 
 // Kernel launchers (enqueue only; return hipError_t of the launch).
 // a1; writes R both as is (roff) and in lattice units (rlat, rlat_h, rlat_b).
@@ -51,8 +58,9 @@ hipError_t launch_rotate(const SlotDev &sd, const float2 *y, int T, float2 *yt, 
 size_t path_partial_bytes(const SlotDev &sd, int T);
 hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_t *out,
                               int precision, float *part, float *bound, hipStream_t st);
-// Pruning bounds (path 0's metric of every vector, (T, S)) for
-// launch_path_search; run before it on the same stream.
+// Pruning record (path 0's metric and decisions of every vector,
+// bound_record_bytes) for launch_path_search; run before it on the same
+// stream (or joined to it by an event).
 hipError_t launch_path_bound(const SlotDev &sd, const float2 *yt, int T, int precision, float *bound,
                              hipStream_t st);
 hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, float sigma2,
@@ -72,7 +80,7 @@ hipError_t launch_mmse(const float2 *H, const float2 *y, int S, int T, int M, in
 // workgroup (threads * vpw <= 256).
 hipError_t launch_path_search_multi(const JobDev *jobs_dev, int n_jobs, int total_items, int N, int bits,
                                     int precision, int threads, int vpw, hipStream_t st);
-// Pruning bounds (path 0's metric per vector) for the jobs of a multi-job
+// Pruning records (path 0 of every vector) for the jobs of a multi-job
 // launch whose JobDev::bound is set: S * ceil(T / 64) items per job, numbered
 // from JobDev::bound_begin.  Run before launch_path_search_multi.
 hipError_t launch_path_bound_multi(const JobDev *jobs_dev, int n_jobs, int bound_items, int N, int bits,

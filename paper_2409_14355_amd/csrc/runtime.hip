@@ -320,7 +320,7 @@ size_t job_device_bytes(const mpnl_job &j)
     sd.N = j.N;
     sd.K = K;
     return align_up(L.total) + align_up((size_t)j.T * j.S * j.N * sizeof(float2)) +
-           align_up((size_t)j.T * j.S * sizeof(float)) + align_up(path_partial_bytes(sd, j.T)) +
+           align_up(bound_record_bytes(j.S, j.T, j.N)) + align_up(path_partial_bytes(sd, j.T)) +
            align_up(sizeof(JobDev));
 }
 
@@ -404,7 +404,7 @@ int detect_impl(mpnl_ctx *ctx, mpnl_slot *slot, const void *y, int T, int32_t *o
         return MPNL_E_UNSUPPORTED;
     const size_t yt_bytes = align_up((size_t)T * sd.S * sd.N * sizeof(float2));
     const size_t part_bytes = align_up(soft ? 0 : mpnl::path_partial_bytes(sd, T));
-    const size_t bound_bytes = (!soft && ctx->prune) ? align_up((size_t)T * sd.S * sizeof(float)) : 0;
+    const size_t bound_bytes = (!soft && ctx->prune) ? align_up(mpnl::bound_record_bytes(sd.S, T, sd.N)) : 0;
     int blk = -1;
     int rc = pool_alloc(ctx, yt_bytes + part_bytes + bound_bytes, st, &blk);
     if (rc != MPNL_OK)
@@ -461,7 +461,7 @@ int oneshot_impl(mpnl_ctx *ctx, const void *H, const void *y, int S, int T, int 
     const mpnl::SlotDev &sd = slot->sd;
     const size_t yt_bytes = align_up((size_t)T * S * N * sizeof(float2));
     const size_t part_bytes = align_up(mpnl::path_partial_bytes(sd, T));
-    const size_t bound_bytes = ctx->prune ? align_up((size_t)T * S * sizeof(float)) : 0;
+    const size_t bound_bytes = ctx->prune ? align_up(mpnl::bound_record_bytes(S, T, N)) : 0;
     int blk = -1;
     rc = pool_alloc(ctx, yt_bytes + part_bytes + bound_bytes, st, &blk);
     if (rc != MPNL_OK) {
@@ -773,7 +773,7 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
         }
         batched[i] = 1;
         rc = pool_alloc(ctx, align_up((size_t)j.T * j.S * j.N * sizeof(float2)) +
-                                 (ctx->prune ? (size_t)j.T * j.S * sizeof(float) : 0),
+                                 (ctx->prune ? mpnl::bound_record_bytes(j.S, j.T, j.N) : 0),
                         st, &ytb[i]);
         if (rc != MPNL_OK)
             break;
@@ -1258,7 +1258,7 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
         total += align_up((size_t)j.T * j.S * j.N * sizeof(float2));
         boff[i] = total;
         if (ctx->prune)
-            total += align_up((size_t)j.T * j.S * sizeof(float));
+            total += align_up(mpnl::bound_record_bytes(j.S, j.T, j.N));
     }
     // launch groups
     auto group = [&](int kind, int param, int bits, int threads) -> PlanLaunch & {
