@@ -331,7 +331,7 @@ __device__ __forceinline__ void kth_wave(bool need, float zI, float zQ, int k, f
 struct PathArgs {
     const float2 *yt;      // (T, S, N) rotated received vectors, lattice units
     const float4 *diag;    // (S, N) (a^2 or 1, R_ll == 0, 1/a or 1, R_ll)
-    const float2 *rlat;    // (S, N, N) R in lattice units
+    const float2 *rlat;    // (S, N, N) R' transposed, lattice units: [d][e] = coefficient of s_e in row d
     const uint32_t *rq;    // (S, N, N) half2 / bf16x2 of rlat, or null
     const int32_t *permd;  // (S, N)
     const uint8_t *P;      // (S, K, NP)
@@ -375,21 +375,66 @@ __device__ __forceinline__ float square_rn(float x)
     return x * x;
 }
 
-// One SIC descent from the residuals b (yt of the vector) driven by the
-// position vector in pw.  After each decision the residuals of the depths
-// below are updated, b_e -= R'[d][e] s_d.  `prune`: the wave stops once every
-// lane with live = true has a metric above it (all lanes must take part).
-// FIRST: every rank is 1 (path 0), the choice code for higher ranks is left out.
-template <int N, int L, int PREC, bool FIRST = false>
-__device__ __forceinline__ float descend(float2 (&b)[N], cptr<float> dg, cptr<float> rl, cptr<uint32_t> rq,
+// Received values of one descent: yt of the vector in depth order, read
+// where each depth needs it, from a wave-uniform pointer (scalar loads) ...
+struct YUniform {
+    cptr<float> p;
+    __device__ __forceinline__ float2 operator()(int d) const { return ld2(p, d); }
+};
+// ... or from registers loaded up front (one received vector per lane).
+template <int N>
+struct YLanes {
+    float2 v[N];
+    __device__ __forceinline__ float2 operator()(int d) const { return v[d]; }
+};
+
+// One SIC descent driven by the position vector in pw, left-looking: the
+// residual of depth d is formed when depth d is reached, y_d minus R'[e][d]
+// s_e for the depths e above it, accumulated in depth order (the same
+// operations in the same order as updating every lower row after each
+// decision, so the same bits), and a wavefront that stops early never
+// computes the rows below.  rl holds R' transposed: rl[d N + e] is the
+// coefficient of s_e in row d (lattice units of row d).  `prune`: the wave
+// stops once every lane with live = true has a metric above it (all lanes
+// must take part).  FIRST: every rank is 1 (path 0), the choice code for
+// higher ranks is left out.
+template <int N, int L, int PREC, bool FIRST = false, typename YF>
+__device__ __forceinline__ float descend(const YF &y, cptr<float> dg, cptr<float> rl, cptr<uint32_t> rq,
                                          const uint32_t *pw, float *decf, float prune, bool live)
 {
     float metric = 0.f;
+    float2 sv[N];                  // FP32: (s_I, s_Q) of the decided depths
+    uint32_t sa[N], sb[N];         // FP16 / BF16: packed (-s_I, s_Q) and (-s_Q, -s_I)
 #pragma unroll
     for (int d = 0; d < N; ++d) {
         const int k = (pw[d >> 2] >> ((d & 3) * 8)) & 0xff;
         const float gw = dg[4 * d], gzero = dg[4 * d + 1];
-        const float zI = b[d].x, zQ = b[d].y;
+        const float2 yd = y(d);
+        float zI = yd.x, zQ = yd.y;
+        if constexpr (PREC == PREC_FP32) {
+#pragma unroll
+            for (int e = 0; e < d; ++e) {
+                const float2 r = ld2(rl, d * N + e);
+                zI = fmaf(-r.x, sv[e].x, zI);
+                zI = fmaf(r.y, sv[e].y, zI);
+                zQ = fmaf(-r.x, sv[e].y, zQ);
+                zQ = fmaf(-r.y, sv[e].x, zQ);
+            }
+        } else if constexpr (PREC == PREC_FP16) {
+#pragma unroll
+            for (int e = 0; e < d; ++e) {
+                const half2_t r = __builtin_bit_cast(half2_t, rq[d * N + e]);
+                zI = __builtin_amdgcn_fdot2(r, __builtin_bit_cast(half2_t, sa[e]), zI, false);
+                zQ = __builtin_amdgcn_fdot2(r, __builtin_bit_cast(half2_t, sb[e]), zQ, false);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < d; ++e) {
+                const bf162_t r = __builtin_bit_cast(bf162_t, rq[d * N + e]);
+                zI = __builtin_amdgcn_fdot2_f32_bf16(r, __builtin_bit_cast(bf162_t, sa[e]), zI, false);
+                zQ = __builtin_amdgcn_fdot2_f32_bf16(r, __builtin_bit_cast(bf162_t, sb[e]), zQ, false);
+            }
+        }
         float mI, mQ, eI, eQ;
         if (gzero != 0.f) {
             // R_ll = 0: every point is equally far; the k-th in index order
@@ -429,38 +474,23 @@ __device__ __forceinline__ float descend(float2 (&b)[N], cptr<float> dg, cptr<fl
             break;
         const float sI = level_of<L>(mI), sQ = level_of<L>(mQ);
         if constexpr (PREC == PREC_FP32) {
-#pragma unroll
-            for (int e = d + 1; e < N; ++e) {
-                const float2 r = ld2(rl, d * N + e);
-                b[e].x = fmaf(-r.x, sI, b[e].x);
-                b[e].x = fmaf(r.y, sQ, b[e].x);
-                b[e].y = fmaf(-r.x, sQ, b[e].y);
-                b[e].y = fmaf(-r.y, sI, b[e].y);
-            }
+            sv[d] = make_float2(sI, sQ);
         } else if constexpr (PREC == PREC_FP16) {
-            half2_t sa, sb;  // (-sI, sQ) and (-sQ, -sI): small odd integers, exact
-            sa.x = (_Float16)(-sI);
-            sa.y = (_Float16)sQ;
-            sb.x = (_Float16)(-sQ);
-            sb.y = (_Float16)(-sI);
-#pragma unroll
-            for (int e = d + 1; e < N; ++e) {
-                const half2_t r = __builtin_bit_cast(half2_t, rq[d * N + e]);
-                b[e].x = __builtin_amdgcn_fdot2(r, sa, b[e].x, false);
-                b[e].y = __builtin_amdgcn_fdot2(r, sb, b[e].y, false);
-            }
+            half2_t ha, hb;  // small odd integers, exact
+            ha.x = (_Float16)(-sI);
+            ha.y = (_Float16)sQ;
+            hb.x = (_Float16)(-sQ);
+            hb.y = (_Float16)(-sI);
+            sa[d] = __builtin_bit_cast(uint32_t, ha);
+            sb[d] = __builtin_bit_cast(uint32_t, hb);
         } else {
-            bf162_t sa, sb;
-            sa.x = (__bf16)(-sI);
-            sa.y = (__bf16)sQ;
-            sb.x = (__bf16)(-sQ);
-            sb.y = (__bf16)(-sI);
-#pragma unroll
-            for (int e = d + 1; e < N; ++e) {
-                const bf162_t r = __builtin_bit_cast(bf162_t, rq[d * N + e]);
-                b[e].x = __builtin_amdgcn_fdot2_f32_bf16(r, sa, b[e].x, false);
-                b[e].y = __builtin_amdgcn_fdot2_f32_bf16(r, sb, b[e].y, false);
-            }
+            bf162_t ha, hb;
+            ha.x = (__bf16)(-sI);
+            ha.y = (__bf16)sQ;
+            hb.x = (__bf16)(-sQ);
+            hb.y = (__bf16)(-sI);
+            sa[d] = __builtin_bit_cast(uint32_t, ha);
+            sb[d] = __builtin_bit_cast(uint32_t, hb);
         }
     }
     return (metric == metric) ? metric : INFINITY;
@@ -551,12 +581,8 @@ __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cp
 #pragma unroll
         for (int w = 0; w < NW; ++w)
             pw[w] = valid ? Pw[(size_t)r * nw + w] : 0x01010101u;
-        float2 b[N];
-#pragma unroll
-        for (int d = 0; d < N; ++d)
-            b[d] = ld2(yv, d);
         const bool known = valid && r == 0 && b0d != nullptr;
-        const float m = descend<N, L, PREC>(b, dg, rl, rq, pw, decf, prune, valid && !known);
+        const float m = descend<N, L, PREC>(YUniform{yv}, dg, rl, rq, pw, decf, prune, valid && !known);
         if (valid) {
             bm = known ? b0 : m;
             br = r;
@@ -665,11 +691,7 @@ __device__ __forceinline__ void soft_vector(const PathArgs &a, int s, int t, uns
             pw[w] = valid ? Pw[(size_t)r * nw + w] : 0x01010101u;
             decf[w] = 0.f;
         }
-        float2 b[N];
-#pragma unroll
-        for (int d = 0; d < N; ++d)
-            b[d] = ld2(yv, d);
-        const float m = descend<N, L, PREC_FP32>(b, dg, rl, nullptr, pw, decf, INFINITY, valid);
+        const float m = descend<N, L, PREC_FP32>(YUniform{yv}, dg, rl, nullptr, pw, decf, INFINITY, valid);
         if (valid) {
             mets[r] = m;
 #pragma unroll
@@ -793,11 +815,11 @@ __device__ __forceinline__ void bound_body(const float2 *yt, cptr<float> dg, cpt
     constexpr int NW = (N + 3) / 4;
     const int t = t0 + (int)(threadIdx.x & 63u);
     const int tt = min(t, T - 1);
-    float2 b[N];
+    YLanes<N> yl;
     const float2 *yv = yt + ((size_t)tt * S + s) * N;
 #pragma unroll
     for (int d = 0; d < N; ++d)
-        b[d] = yv[d];
+        yl.v[d] = yv[d];
     uint32_t pw[NW];
     float decf[NW];
 #pragma unroll
@@ -805,7 +827,7 @@ __device__ __forceinline__ void bound_body(const float2 *yt, cptr<float> dg, cpt
         pw[w] = 0x01010101u;
         decf[w] = 0.f;
     }
-    const float m = descend<N, L, PREC, true>(b, dg, rl, rq, pw, decf, INFINITY, true);
+    const float m = descend<N, L, PREC, true>(yl, dg, rl, rq, pw, decf, INFINITY, true);
     if (t < T) {
         const size_t v = (size_t)t * S + s;
         bound[v] = m;

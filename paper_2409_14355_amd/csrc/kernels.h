@@ -14,7 +14,8 @@ struct SlotDev {
     int NP;                // position-vector row stride in bytes (N rounded up to 4)
     float2 *Qd;            // (S, M, N)  column d = Q[:, N-1-d]
     float2 *roff;          // (S, N, N)  [d][d'] = R[N-1-d'][N-1-d] for d' > d
-    float2 *rlat;          // (S, N, N)  the same entries in lattice units, times Delta / a_{d'}
+    float2 *rlat;          // (S, N, N)  the same entries in lattice units, times Delta / a_{d'},
+                           //            transposed: [d'][d] (row d', term of depth d < d')
     uint32_t *rlat_h;      // (S, N, N)  rlat as half2 (MPNL_PREC_FP16)
     uint32_t *rlat_b;      // (S, N, N)  rlat as bf16x2 (MPNL_PREC_BF16)
     float4 *diag;          // (S, N)     (a^2 or 1, R_ll == 0, 1/a or 1, R_ll), a = R_ll Delta

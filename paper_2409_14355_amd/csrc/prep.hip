@@ -161,13 +161,14 @@ __device__ __forceinline__ void sqrd_body(const SqrdArgs &a, int pair)
         for (int m = 0; m < MMAX; ++m) {
             if (m < pos) {
                 const int d2 = N - 1 - m;
-                const size_t o = (sN + d) * N + d2;
+                const size_t o = (sN + d) * N + d2;   // roff: [d][d2]
+                const size_t ot = (sN + d2) * N + d;  // lattice copies transposed: row d2, term of depth d
                 const float sc = a.delta * INVA[half][m];
                 const float lx = col[m].x * sc, ly = col[m].y * sc;
                 a.sd.roff[o] = col[m];
-                a.sd.rlat[o] = make_float2(lx, ly);
-                a.sd.rlat_h[o] = pack_half2(lx, ly);
-                a.sd.rlat_b[o] = bf16_bits(lx) | (bf16_bits(ly) << 16);
+                a.sd.rlat[ot] = make_float2(lx, ly);
+                a.sd.rlat_h[ot] = pack_half2(lx, ly);
+                a.sd.rlat_b[ot] = bf16_bits(lx) | (bf16_bits(ly) << 16);
             }
         }
     }

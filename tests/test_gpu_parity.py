@@ -141,6 +141,9 @@ CASES = [
     ("6x5-qam16-K1000", 9, 17, 6, 5, 4, 12, 1000, "iid"),
     ("3x1-qam64-K8", 33, 3, 3, 1, 6, 15, 8, "iid"),
     ("7x3-qpsk-K100-odd", 15, 2, 7, 3, 2, 5, 100, "iid"),
+    ("12x8-qam16-K1-sic", 50, 7, 12, 8, 4, 16, 1, "iid"),      # path 0 alone: ordered SIC
+    ("6x6-qpsk-K2", 40, 5, 6, 6, 2, 6, 2, "kron"),
+    ("4x3-qam16-K4096-all", 12, 3, 4, 3, 4, 8, 4096, "iid"),  # every vector: ML
 ]
 
 
