@@ -263,12 +263,13 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
 #pragma unroll
         for (int q = 0; q < kMaxN / 4; ++q)
             wvd[q] = 0x01010101u;
-        uint32_t m3 = 0, m2 = 0;
+        uint32_t m5 = 0, m3 = 0, m2 = 0;
         int pidx = r;
         for (int d = N - 1; d >= 0; --d) {
             const uint32_t e = rec[(size_t)d * KP + pidx];
             const uint32_t pk = (e >> 8) + 1u;
             pidx = (int)(e & 0xffu);
+            m5 |= (pk >= 5u ? 1u : 0u) << d;
             m3 |= (pk >= 3u ? 1u : 0u) << d;
             m2 |= (pk >= 2u ? 1u : 0u) << d;
 #pragma unroll
@@ -283,12 +284,17 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
                 dst[q] = wvd[q];
         // sort key: the first depth with a rank >= 2 (paths that leave the
         // first-choice path early are pruned early, and the pruning stops
-        // whole wavefronts), then the depths with rank >= 3, then a fold of
-        // the depths with rank >= 2 (the key only groups paths; any order is
-        // correct)
+        // whole wavefronts), the first depths with a rank >= 3 and >= 5 (the
+        // costly point choices start together), then folds of the depths
+        // with rank >= 3 and >= 2 (the key only groups paths; any order is
+        // correct).  Fields: 6 + 6 + 6 + 20 + 15 bits, exact in a double.
         const uint32_t fd = m2 ? (uint32_t)__builtin_ctz(m2) : (uint32_t)N;
+        const uint32_t f3 = m3 ? (uint32_t)__builtin_ctz(m3) : (uint32_t)N;
+        const uint32_t f5 = m5 ? (uint32_t)__builtin_ctz(m5) : (uint32_t)N;
+        const uint32_t m3f = (m3 ^ (m3 >> 20)) & 0xfffffu;
         const uint32_t m2f = (m2 ^ (m2 >> 15) ^ (m2 >> 30)) & 0x7fffu;
-        ks = (double)fd * 140737488355328.0 + (double)m3 * 32768.0 + (double)m2f;  // 2^47, 2^15
+        ks = (double)fd * 140737488355328.0 + (double)f3 * 2199023255552.0 + (double)f5 * 34359738368.0 +
+             (double)m3f * 32768.0 + (double)m2f;  // 2^47, 2^41, 2^35, 2^15
     }
     // Lane order: paths sorted by that key, so that the lanes of one
     // wavefront leave path 0 at about the same depth and need the costly
