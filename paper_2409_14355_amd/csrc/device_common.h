@@ -388,6 +388,27 @@ struct YLanes {
     __device__ __forceinline__ float2 operator()(int d) const { return v[d]; }
 };
 
+// The subcarrier's triangular factor as the descent reads it: the diagonal
+// record (a^2, R_ll == 0 flag, ...) per depth and R' transposed (rl, FP32;
+// rq, packed FP16 / BF16), through a wave-uniform pointer (scalar loads) ...
+struct RUniform {
+    cptr<float> dg, rl;
+    cptr<uint32_t> rq;
+    __device__ __forceinline__ float gw(int d) const { return dg[4 * d]; }
+    __device__ __forceinline__ float gzero(int d) const { return dg[4 * d + 1]; }
+    __device__ __forceinline__ float2 r(int i) const { return ld2(rl, i); }
+    __device__ __forceinline__ uint32_t q(int i) const { return rq[i]; }
+};
+// ... or through a pointer of each lane's own subcarrier (vector loads).
+struct RLanes {
+    const float *dg, *rl;
+    const uint32_t *rq;
+    __device__ __forceinline__ float gw(int d) const { return dg[4 * d]; }
+    __device__ __forceinline__ float gzero(int d) const { return dg[4 * d + 1]; }
+    __device__ __forceinline__ float2 r(int i) const { return ((const float2 *)rl)[i]; }
+    __device__ __forceinline__ uint32_t q(int i) const { return rq[i]; }
+};
+
 // One SIC descent driven by the position vector in pw, left-looking: the
 // residual of depth d is formed when depth d is reached, y_d minus R'[e][d]
 // s_e for the depths e above it, accumulated in depth order (the same
@@ -398,9 +419,9 @@ struct YLanes {
 // stops once every lane with live = true has a metric above it (all lanes
 // must take part).  FIRST: every rank is 1 (path 0), the choice code for
 // higher ranks is left out.
-template <int N, int L, int PREC, bool FIRST = false, typename YF>
-__device__ __forceinline__ float descend(const YF &y, cptr<float> dg, cptr<float> rl, cptr<uint32_t> rq,
-                                         const uint32_t *pw, float *decf, float prune, bool live)
+template <int N, int L, int PREC, bool FIRST = false, typename YF, typename RF>
+__device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_t *pw, float *decf, float prune,
+                                         bool live)
 {
     float metric = 0.f;
     float2 sv[N];                  // FP32: (s_I, s_Q) of the decided depths
@@ -408,13 +429,13 @@ __device__ __forceinline__ float descend(const YF &y, cptr<float> dg, cptr<float
 #pragma unroll
     for (int d = 0; d < N; ++d) {
         const int k = (pw[d >> 2] >> ((d & 3) * 8)) & 0xff;
-        const float gw = dg[4 * d], gzero = dg[4 * d + 1];
+        const float gw = R.gw(d), gzero = R.gzero(d);
         const float2 yd = y(d);
         float zI = yd.x, zQ = yd.y;
         if constexpr (PREC == PREC_FP32) {
 #pragma unroll
             for (int e = 0; e < d; ++e) {
-                const float2 r = ld2(rl, d * N + e);
+                const float2 r = R.r(d * N + e);
                 zI = fmaf(-r.x, sv[e].x, zI);
                 zI = fmaf(r.y, sv[e].y, zI);
                 zQ = fmaf(-r.x, sv[e].y, zQ);
@@ -423,14 +444,14 @@ __device__ __forceinline__ float descend(const YF &y, cptr<float> dg, cptr<float
         } else if constexpr (PREC == PREC_FP16) {
 #pragma unroll
             for (int e = 0; e < d; ++e) {
-                const half2_t r = __builtin_bit_cast(half2_t, rq[d * N + e]);
+                const half2_t r = __builtin_bit_cast(half2_t, R.q(d * N + e));
                 zI = __builtin_amdgcn_fdot2(r, __builtin_bit_cast(half2_t, sa[e]), zI, false);
                 zQ = __builtin_amdgcn_fdot2(r, __builtin_bit_cast(half2_t, sb[e]), zQ, false);
             }
         } else {
 #pragma unroll
             for (int e = 0; e < d; ++e) {
-                const bf162_t r = __builtin_bit_cast(bf162_t, rq[d * N + e]);
+                const bf162_t r = __builtin_bit_cast(bf162_t, R.q(d * N + e));
                 zI = __builtin_amdgcn_fdot2_f32_bf16(r, __builtin_bit_cast(bf162_t, sa[e]), zI, false);
                 zQ = __builtin_amdgcn_fdot2_f32_bf16(r, __builtin_bit_cast(bf162_t, sb[e]), zQ, false);
             }
@@ -582,7 +603,7 @@ __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cp
         for (int w = 0; w < NW; ++w)
             pw[w] = valid ? Pw[(size_t)r * nw + w] : 0x01010101u;
         const bool known = valid && r == 0 && b0d != nullptr;
-        const float m = descend<N, L, PREC>(YUniform{yv}, dg, rl, rq, pw, decf, prune, valid && !known);
+        const float m = descend<N, L, PREC>(YUniform{yv}, RUniform{dg, rl, rq}, pw, decf, prune, valid && !known);
         if (valid) {
             bm = known ? b0 : m;
             br = r;
@@ -691,7 +712,7 @@ __device__ __forceinline__ void soft_vector(const PathArgs &a, int s, int t, uns
             pw[w] = valid ? Pw[(size_t)r * nw + w] : 0x01010101u;
             decf[w] = 0.f;
         }
-        const float m = descend<N, L, PREC_FP32>(YUniform{yv}, dg, rl, nullptr, pw, decf, INFINITY, valid);
+        const float m = descend<N, L, PREC_FP32>(YUniform{yv}, RUniform{dg, rl, nullptr}, pw, decf, INFINITY, valid);
         if (valid) {
             mets[r] = m;
 #pragma unroll
@@ -804,22 +825,25 @@ __global__ __launch_bounds__(256) void path_search_multi_kernel(MultiArgs a)
 // ============================================================================
 // Pruning record: path 0 (first choice at every depth) of every received
 // vector, computed with the same descent as the path search; the metrics,
-// (T, S) floats, then the packed decisions, (T, S, (N + 3) / 4) floats.  A
-// wavefront per (subcarrier, 64 symbols); lane t runs symbol t0 + t (lanes
-// past the last symbol repeat it and write nothing).
-// ============================================================================
+// (T, S) floats, then the packed decisions, (T, S, (N + 3) / 4) floats.
+// One lane per received vector, vectors numbered subcarrier-major (index
+// s T + t), so the lanes of a wavefront share few subcarriers and every lane
+// does work; R is read through each lane's own subcarrier.
 template <int N, int L, int PREC>
-__device__ __forceinline__ void bound_body(const float2 *yt, cptr<float> dg, cptr<float> rl, cptr<uint32_t> rq,
-                                           int S, int T, int s, int t0, float *bound)
+__device__ __forceinline__ void bound_body(const float2 *yt, const float4 *diag, const float2 *rlat,
+                                           const uint32_t *rq, int S, int T, int i0, float *bound)
 {
     constexpr int NW = (N + 3) / 4;
-    const int t = t0 + (int)(threadIdx.x & 63u);
-    const int tt = min(t, T - 1);
+    const int i = i0 + (int)(threadIdx.x & 63u);
+    const int ic = min(i, S * T - 1);
+    const int s = ic / T, t = ic - s * T;
+    const size_t sN = (size_t)s * N;
     YLanes<N> yl;
-    const float2 *yv = yt + ((size_t)tt * S + s) * N;
+    const float2 *yv = yt + ((size_t)t * S + s) * N;
 #pragma unroll
     for (int d = 0; d < N; ++d)
         yl.v[d] = yv[d];
+    const RLanes R{(const float *)(diag + sN), (const float *)(rlat + sN * N), rq ? rq + sN * N : nullptr};
     uint32_t pw[NW];
     float decf[NW];
 #pragma unroll
@@ -827,8 +851,8 @@ __device__ __forceinline__ void bound_body(const float2 *yt, cptr<float> dg, cpt
         pw[w] = 0x01010101u;
         decf[w] = 0.f;
     }
-    const float m = descend<N, L, PREC, true>(yl, dg, rl, rq, pw, decf, INFINITY, true);
-    if (t < T) {
+    const float m = descend<N, L, PREC, true>(yl, R, pw, decf, INFINITY, true);
+    if (i < S * T) {
         const size_t v = (size_t)t * S + s;
         bound[v] = m;
         float *dec = bound + (size_t)S * T + v * NW;
@@ -838,20 +862,15 @@ __device__ __forceinline__ void bound_body(const float2 *yt, cptr<float> dg, cpt
     }
 }
 
-// grid: S * ceil(T / 64) wavefronts
+// grid: ceil(S * T / 64) wavefronts
 template <int N, int L, int PREC>
 __global__ __launch_bounds__(64) void path_bound_kernel(PathArgs a)
 {
-    const int chunks = (a.T + 63) / 64;
-    const int s = blockIdx.x / chunks, t0 = (blockIdx.x - s * chunks) * 64;
-    const size_t sN = (size_t)s * N;
-    cptr<uint32_t> rq = a.rq ? uniform_ptr(a.rq + sN * N) : nullptr;
-    bound_body<N, L, PREC>(a.yt, uniform_ptr(a.diag + sN), uniform_ptr(a.rlat + sN * N), rq, a.S, a.T, s, t0,
-                           a.bound);
+    bound_body<N, L, PREC>(a.yt, a.diag, a.rlat, a.rq, a.S, a.T, (int)blockIdx.x * 64, a.bound);
 }
 
-// Many jobs of one (N, L): item = (job, subcarrier, 64-symbol chunk), numbered
-// job by job from JobDev::bound_begin.
+// Many jobs of one (N, L): item = (job, 64 received vectors), numbered job by
+// job from JobDev::bound_begin (ceil(S * T / 64) items a job).
 __device__ __forceinline__ int find_bound_job(const JobDev *jobs, int n_jobs, int item)
 {
     int lo = 0, hi = n_jobs - 1;
@@ -869,13 +888,7 @@ template <int N, int L, int PREC>
 __global__ __launch_bounds__(64) void path_bound_multi_kernel(const JobDev *jobs, int n_jobs)
 {
     const JobDev &j = jobs[find_bound_job(jobs, n_jobs, (int)blockIdx.x)];
-    const int chunks = (j.T + 63) / 64;
-    const int li = (int)blockIdx.x - j.bound_begin;
-    const int s = li / chunks, t0 = (li - s * chunks) * 64;
-    const size_t sN = (size_t)s * N;
-    cptr<uint32_t> rq = j.rq ? uniform_ptr(j.rq + sN * N) : nullptr;
-    bound_body<N, L, PREC>(j.yt, uniform_ptr(j.diag + sN), uniform_ptr(j.rlat + sN * N), rq, j.S, j.T, s, t0,
-                           j.bound);
+    bound_body<N, L, PREC>(j.yt, j.diag, j.rlat, j.rq, j.S, j.T, ((int)blockIdx.x - j.bound_begin) * 64, j.bound);
 }
 
 inline float delta_of(int bits)

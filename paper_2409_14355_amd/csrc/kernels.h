@@ -39,7 +39,7 @@ struct JobDev {
     float *bound;          // pruning record (bound_record_bytes), or null
     int S, T, N, K, NP;
     int item_begin;        // first global work item of this job
-    int bound_begin;       // first item of this job in the bound launch (S * ceil(T / 64) items a job)
+    int bound_begin;       // first item of this job in the bound launch (ceil(S T / 64) items a job)
 };
 
 // Pruning record of a (S, T) job with N users: path 0's metric per vector,
@@ -82,7 +82,7 @@ hipError_t launch_mmse(const float2 *H, const float2 *y, int S, int T, int M, in
 hipError_t launch_path_search_multi(const JobDev *jobs_dev, int n_jobs, int total_items, int N, int bits,
                                     int precision, int threads, int vpw, hipStream_t st);
 // Pruning records (path 0 of every vector) for the jobs of a multi-job
-// launch whose JobDev::bound is set: S * ceil(T / 64) items per job, numbered
+// launch whose JobDev::bound is set: ceil(S T / 64) items per job, numbered
 // from JobDev::bound_begin.  Run before launch_path_search_multi.
 hipError_t launch_path_bound_multi(const JobDev *jobs_dev, int n_jobs, int bound_items, int N, int bits,
                                    int precision, hipStream_t st);

@@ -864,7 +864,7 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
                                                      align_up((size_t)jobs[i].T * sd.S * sd.N * sizeof(float2)))
                                          : nullptr;
                     J.bound_begin = bacc;
-                    bacc += sd.S * ((jobs[i].T + 63) / 64);
+                    bacc += (sd.S * jobs[i].T + 63) / 64;
                     J.rlat = sd.rlat;
                     J.rq = rq_of(sd, ctx->precision);
                     J.diag = sd.diag;
@@ -1044,7 +1044,7 @@ void plan_fill(mpnl_batch *p, int b, const mpnl_job *jobs)
                 J.yt = p->yt[i];
                 J.bound = p->bound[i];
                 J.bound_begin = bacc;
-                bacc += sd.S * ((jobs[i].T + 63) / 64);
+                bacc += (sd.S * jobs[i].T + 63) / 64;
                 J.rlat = sd.rlat;
                 J.rq = rq_of(sd, p->precision);
                 J.diag = sd.diag;
@@ -1292,7 +1292,7 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
             } else {
                 L = &group(L_PATHS, j.N, j.mod, (K + 63) / 64 * 64);
                 L->items += j.S * j.T;
-                L->bound_items += j.S * ((j.T + 63) / 64);
+                L->bound_items += (j.S * j.T + 63) / 64;
             }
             L->jobs.push_back(i);
         }
