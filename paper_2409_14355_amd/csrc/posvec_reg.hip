@@ -13,10 +13,9 @@
 // Every merge is a bitonic network: thread g holds entry g of the list
 // (g = 64 w + lane for wavefront w).  One half-cleaner stage compares U_j
 // with the reversed raised list, then log2(64 E) compare-exchange stages sort
-// the K smallest.  The half cleaner and the stages across wavefronts go
-// through one exchange in LDS (double-buffered, one barrier per merge: every
-// lane gathers its column l, l + 64, ... and runs those stages in registers),
-// the stages inside a wavefront use DPP / row-swap lane exchanges.  An entry
+// the K smallest.  The half cleaner and each stage across wavefronts go
+// through LDS (alternating buffers, one barrier each), the stages inside a
+// wavefront use DPP / row-swap lane exchanges.  An entry
 // is (score, packed) with packed = parent position (12 bits) | k (6 bits)
 // << 12 | lexical rank of the parent (14 bits) << 18, so the key
 // (score, parent rank, k) compares as (score, packed).
@@ -54,26 +53,6 @@ __device__ __forceinline__ void lane_stage(double &cs, uint32_t &cp, int s, bool
     const bool take = (lower == asc) == key_lt(os, op, cs, cp);
     cs = take ? os : cs;
     cp = take ? op : cp;
-}
-
-// Entry `pos` of the column of E entries after the register stages
-// js = E/2 .. 1 (entry distance 64 js) of an ascending bitonic merge.  The
-// entry at pos is the min or the max (bit js of pos) of a pair at every stage,
-// so only the E - 1 pairs on its way are compared.  `pos` is the same in
-// every lane of the wavefront.
-template <int E>
-__device__ __forceinline__ void column_pick(double (&cs)[E], uint32_t (&cp)[E], int pos)
-{
-#pragma unroll
-    for (int js = E / 2; js >= 1; js >>= 1) {
-        const bool want_max = (pos & js) != 0;
-#pragma unroll
-        for (int j = 0; j < js; ++j) {
-            const bool take_hi = key_lt(cs[j + js], cp[j + js], cs[j], cp[j]) != want_max;
-            cs[j] = take_hi ? cs[j + js] : cs[j];
-            cp[j] = take_hi ? cp[j + js] : cp[j];
-        }
-    }
 }
 
 // Inclusive prefix sum over the 64 lanes: four row shifts inside each row of
@@ -170,8 +149,7 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
                 cs[0] = tb ? cs[0] : Zs;
                 cp[0] = tb ? cp[0] : Zp;
             } else {
-                sh.xs[buf][0][g] = Zs;
-                sh.xp[buf][0][g] = Zp;
+                buf ^= 1;
                 sh.xs[buf][1][g] = Bs;
                 sh.xp[buf][1][g] = Bp;
                 if (g == K - 1) {
@@ -191,20 +169,29 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
                     break;
             }
             if constexpr (E > 1) {
-                // half cleaner on the column (entry j * 64 + lane against
-                // entry KP - 1 - (j * 64 + lane) of B), then the stages across
-                // wavefronts
-#pragma unroll
-                for (int j = 0; j < E; ++j) {
-                    const int e = j * 64 + lane;
-                    const double zs = sh.xs[buf][0][e], rs = sh.xs[buf][1][KP - 1 - e];
-                    const uint32_t zp = sh.xp[buf][0][e], rp = sh.xp[buf][1][KP - 1 - e];
-                    const bool tb = key_lt(rs, rp, zs, zp);
-                    cs[j] = tb ? rs : zs;
-                    cp[j] = tb ? rp : zp;
+                // half cleaner (entry g against entry KP - 1 - g of B), then
+                // the stages across wavefronts, one LDS exchange each
+                // (alternating buffers: one barrier per exchange)
+                {
+                    const double rs = sh.xs[buf][1][KP - 1 - g];
+                    const uint32_t rp = sh.xp[buf][1][KP - 1 - g];
+                    const bool tb = key_lt(rs, rp, Zs, Zp);
+                    cs[0] = tb ? rs : Zs;
+                    cp[0] = tb ? rp : Zp;
                 }
-                column_pick<E>(cs, cp, wv);
-                buf ^= 1;
+#pragma unroll
+                for (int js = E / 2; js >= 1; js >>= 1) {
+                    buf ^= 1;
+                    sh.xs[buf][0][g] = cs[0];
+                    sh.xp[buf][0][g] = cp[0];
+                    __syncthreads();
+                    const double os = sh.xs[buf][0][g ^ (64 * js)];
+                    const uint32_t op = sh.xp[buf][0][g ^ (64 * js)];
+                    const bool lower = (g & (64 * js)) == 0;
+                    const bool take = lower == key_lt(os, op, cs[0], cp[0]);
+                    cs[0] = take ? os : cs[0];
+                    cp[0] = take ? op : cp[0];
+                }
             }
             Zs = cs[0];
             Zp = cp[0];
