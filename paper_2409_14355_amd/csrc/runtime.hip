@@ -25,6 +25,7 @@ struct Block {
     hipStream_t last_stream = nullptr;
     hipEvent_t ev = nullptr;  // recorded on last_stream when released
     bool ev_pending = false;
+    bool ev_deferred = false;  // released without an event: recorded when another stream asks for it
 };
 
 constexpr size_t kAlign = 256;
@@ -103,11 +104,26 @@ int hip_fail(mpnl_ctx *ctx, hipError_t e)
     return e == hipErrorOutOfMemory ? MPNL_E_NOMEM : MPNL_E_HIP;
 }
 
-bool block_idle(const Block &b, hipStream_t st)
+// A block released with a deferred event gets its event when another stream
+// first asks for it; the event then covers all the work enqueued on the
+// releasing stream so far (a superset of the work that used the block), and
+// the block counts as busy until that has finished.
+void record_deferred(Block &b)
+{
+    if (!b.ev_deferred)
+        return;
+    b.ev_deferred = false;
+    b.ev_pending = hipEventRecord(b.ev, b.last_stream) == hipSuccess;
+}
+
+bool block_idle(Block &b, hipStream_t st)
 {
     if (!b.free)
         return false;
-    if (!b.ev_pending || b.last_stream == st)
+    if (b.last_stream == st)
+        return true;
+    record_deferred(b);
+    if (!b.ev_pending)
         return true;
     return hipEventQuery(b.ev) == hipSuccess;
 }
@@ -120,7 +136,7 @@ int pool_alloc(mpnl_ctx *ctx, size_t bytes, hipStream_t st, int *out_block)
     bytes = align_up(std::max<size_t>(bytes, 1));
     int best = -1;
     for (int i = 0; i < (int)ctx->blocks.size(); ++i) {
-        const Block &b = ctx->blocks[i];
+        Block &b = ctx->blocks[i];
         if (b.size >= bytes && b.size <= 2 * bytes + (1u << 20) && block_idle(b, st)) {
             if (best < 0 || b.size < ctx->blocks[best].size)
                 best = i;
@@ -128,6 +144,7 @@ int pool_alloc(mpnl_ctx *ctx, size_t bytes, hipStream_t st, int *out_block)
     }
     if (best >= 0) {
         ctx->blocks[best].free = false;
+        ctx->blocks[best].ev_deferred = false;
         *out_block = best;
         return MPNL_OK;
     }
@@ -135,6 +152,8 @@ int pool_alloc(mpnl_ctx *ctx, size_t bytes, hipStream_t st, int *out_block)
         // give back idle cached blocks until the request fits
         for (int i = 0; i < (int)ctx->blocks.size() && ctx->held + bytes > ctx->budget; ++i) {
             Block &b = ctx->blocks[i];
+            if (b.ptr && b.free)
+                record_deferred(b);
             if (b.ptr && b.free && (!b.ev_pending || hipEventQuery(b.ev) == hipSuccess)) {
                 (void)hipFree(b.ptr);
                 ctx->held -= b.size;
@@ -170,19 +189,26 @@ int pool_alloc(mpnl_ctx *ctx, size_t bytes, hipStream_t st, int *out_block)
     b.size = bytes;
     b.free = false;
     b.ev_pending = false;
+    b.ev_deferred = false;
     ctx->held += bytes;
     *out_block = slot;
     return MPNL_OK;
 }
 
-void pool_release(mpnl_ctx *ctx, int blk, hipStream_t st)
+// Return a block to the pool after the work enqueued on `st` so far.  With
+// `defer`, no event is recorded now (an event on the stream costs a few
+// microseconds of device time): the block is reused at once on `st`, and its
+// event is recorded only when another stream asks for it, so `st` must still
+// exist then (callers defer only on the null stream).
+void pool_release(mpnl_ctx *ctx, int blk, hipStream_t st, bool defer = false)
 {
     if (blk < 0 || blk >= (int)ctx->blocks.size())
         return;
     Block &b = ctx->blocks[blk];
     b.free = true;
     b.last_stream = st;
-    b.ev_pending = hipEventRecord(b.ev, st) == hipSuccess;
+    b.ev_deferred = defer;
+    b.ev_pending = defer ? false : hipEventRecord(b.ev, st) == hipSuccess;
 }
 
 hipEvent_t take_event(mpnl_ctx *ctx)
@@ -384,9 +410,9 @@ int prepare_impl(mpnl_ctx *ctx, const void *H, int S, int M, int N, int mod, int
     return MPNL_OK;
 }
 
-void release_impl(mpnl_ctx *ctx, mpnl_slot *slot)
+void release_impl(mpnl_ctx *ctx, mpnl_slot *slot, bool defer = false)
 {
-    pool_release(ctx, slot->block, slot->stream);
+    pool_release(ctx, slot->block, slot->stream, defer);
     ctx->slots.erase(std::remove(ctx->slots.begin(), ctx->slots.end(), slot), ctx->slots.end());
     delete slot;
 }
@@ -429,7 +455,7 @@ int detect_impl(mpnl_ctx *ctx, mpnl_slot *slot, const void *y, int T, int32_t *o
         else
             e = mpnl::launch_path_search(sd, yt, T, out, ctx->precision, part, bound, st);
     }
-    pool_release(ctx, blk, st);
+    pool_release(ctx, blk, st, st == nullptr);  // per-call workspace (see oneshot_impl)
     slot->stream = st;
     if (e != hipSuccess)
         return hip_fail(ctx, e);
@@ -495,9 +521,12 @@ int oneshot_impl(mpnl_ctx *ctx, const void *H, const void *y, int S, int T, int 
         StageTimer tm(ctx, MPNL_STAGE_PATHS, st);
         e = mpnl::launch_path_search(sd, yt, T, out, ctx->precision, part, bound, st);
     }
-    pool_release(ctx, blk, st);
+    // per-call workspace, reused at once by the next call on this stream; the
+    // event is deferred only on the null stream (a user stream may be
+    // destroyed before another stream asks for the block)
+    pool_release(ctx, blk, st, st == nullptr);
     slot->stream = st;
-    release_impl(ctx, slot);
+    release_impl(ctx, slot, st == nullptr);
     return e == hipSuccess ? MPNL_OK : hip_fail(ctx, e);
 }
 
