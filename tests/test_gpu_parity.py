@@ -248,6 +248,36 @@ def test_slot_reuse_equals_one_shot(ctx):
     assert torch.equal(a, one) and torch.equal(b, two)
 
 
+def test_workspace_reuse_across_streams(ctx):
+    """One-shot and slot calls on the default stream hand their workspace back
+    to the pool without a stream event; a call on another stream that wants
+    that memory must still wait for the work that used it.  Calls alternate
+    between the default stream and a side stream with similar sizes (so the
+    pool hands the same blocks around), the side stream's calls running while
+    the default stream still works; every result must equal the first one."""
+    _say("workspace across streams")
+    sls = [synth.make_slot(S=S, T=14, M=16, N=16, bits=4, snr_db=14, seed=(211, S)) for S in (300, 280)]
+    dev = [(_dev(sl.H), _dev(sl.y)) for sl in sls]
+    refs = [ctx.detect(H, y, 4, 256) for H, y in dev]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    outs = [(j, torch.full_like(refs[j], -1)) for _ in range(8) for j in range(len(dev))]
+    torch.cuda.synchronize()
+    for i in range(8):
+        st = None if i % 2 == 0 else side
+        for j, (H, y) in enumerate(dev):
+            out = outs[i * len(dev) + j][1]
+            if i % 4 == 3:
+                slot = ctx.slot_prepare(H, 4, 256, stream=st)
+                slot.detect(y, out=out, stream=st)
+                slot.release()
+            else:
+                ctx.detect(H, y, 4, 256, out=out, stream=st)
+    torch.cuda.synchronize()
+    for j, out in outs:
+        assert torch.equal(out, refs[j]), j
+
+
 def test_deterministic_and_batch_equals_alone(ctx):
     _say("batch vs alone")
     shapes = [(120, 14, 8, 6, 2, 64), (75, 14, 16, 16, 4, 128), (40, 14, 32, 20, 6, 256),
