@@ -178,6 +178,17 @@ __device__ __forceinline__ int find_job(const J *jobs, int n_jobs, int item)
 // a4: choice of the k-th closest constellation point at one depth, in lattice
 // units.  Level index m in 0..L-1 <-> level value 2m - (L-1).
 // ============================================================================
+// x * x rounded on its own: never fused into the sum that follows, so every
+// distance of the descent (first choice or k-th) rounds alike in every kernel
+// that runs it, whatever code surrounds it.  The path kernel repeats path 0
+// of the pruning record, and the batched and one-shot kernels of the same
+// job must reach the same bits.
+__device__ __forceinline__ float square_rn(float x)
+{
+#pragma clang fp contract(off)
+    return x * x;
+}
+
 template <int L>
 __device__ __forceinline__ float level_of(float m)
 {
@@ -200,8 +211,7 @@ __device__ __forceinline__ void axis_second(float z, float m0, float lv0, float 
     const float s = (z >= lv0) ? 1.f : -1.f;
     const float a = m0 + s;
     m1 = ((a >= 0.f) & (a <= (float)(L - 1))) ? a : m0 - s;
-    const float d1 = z - level_of<L>(m1);
-    e1 = d1 * d1;
+    e1 = square_rn(z - level_of<L>(m1));
 }
 
 // levels of rank 1..3 of one axis (rank 0 = m0, at level lv0): the zig-zag
@@ -224,7 +234,7 @@ __device__ __forceinline__ void axis_ranks3(float z, float m0, float lv0, float 
         const float mt = ((float)t <= 2.f * q) ? ti : to;
         const float dd = z - level_of<L>(mt);
         m[t - 1] = mt;
-        e[t - 1] = (t <= L - 1) ? dd * dd : INFINITY;
+        e[t - 1] = (t <= L - 1) ? square_rn(dd) : INFINITY;
     }
 }
 
@@ -295,7 +305,7 @@ __device__ __forceinline__ void kth_wave(bool need, float zI, float zQ, int k, f
         const float zi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zI), src));
         const float zq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zQ), src));
         const float dI = zi - vI, dQ = zq - vQ;
-        float key = dI * dI + dQ * dQ;
+        float key = square_rn(dI) + square_rn(dQ);
         int kid = cidx;
 #pragma unroll
         for (int size = 2; size <= NPT; size <<= 1) {
@@ -317,9 +327,8 @@ __device__ __forceinline__ void kth_wave(bool need, float zI, float zQ, int k, f
         if (mine) {
             mI = (float)gray_decode(got >> HB);
             mQ = (float)gray_decode(got & (L - 1));
-            const float eI1 = zI - level_of<L>(mI), eQ1 = zQ - level_of<L>(mQ);
-            eI = eI1 * eI1;
-            eQ = eQ1 * eQ1;
+            eI = square_rn(zI - level_of<L>(mI));
+            eQ = square_rn(zQ - level_of<L>(mQ));
         }
         pend &= ~__ballot(mine);
     }
@@ -366,14 +375,6 @@ __device__ __forceinline__ constexpr float code_weight(int d)
 // pruned path has a metric strictly above the minimum.
 constexpr float kBoundPad = 1.0001f;
 
-// x * x rounded on its own: never fused into the sum that follows, so the
-// first-choice distances (all of path 0's metric) round alike in every
-// instantiation of the descent, whatever branches surround them.
-__device__ __forceinline__ float square_rn(float x)
-{
-#pragma clang fp contract(off)
-    return x * x;
-}
 
 // Received values of one descent: yt of the vector in depth order, read
 // where each depth needs it, from a wave-uniform pointer (scalar loads) ...
