@@ -94,6 +94,35 @@ __device__ __forceinline__ double lane_xor_n(double x, int s)
     return __longlong_as_double((long long)(lo | (hi << 32)));
 }
 
+// Both ends of the distance-S lane pair this lane belongs to, for S = 16 or
+// 32: lo = x of lane (lane & ~S), hi = x of lane (lane | S).  One row or
+// half-wave swap gives both (a compare-exchange then picks from lo and hi by
+// the lane's side, with no select of the partner's value first).
+template <int S>
+__device__ __forceinline__ void lane_pair(uint32_t x, uint32_t &lo, uint32_t &hi)
+{
+    static_assert(S == 16 || S == 32, "lane pairs by swap need a distance of 16 or 32");
+    if constexpr (S == 16) {
+        const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        lo = p[0];
+        hi = p[1];
+    } else {
+        const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        lo = p[0];
+        hi = p[1];
+    }
+}
+template <int S>
+__device__ __forceinline__ void lane_pair(double x, double &lo, double &hi)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    uint32_t l0, h0, l1, h1;
+    lane_pair<S>((uint32_t)u, l0, h0);
+    lane_pair<S>((uint32_t)(u >> 32), l1, h1);
+    lo = __longlong_as_double((long long)((uint64_t)l0 | ((uint64_t)l1 << 32)));
+    hi = __longlong_as_double((long long)((uint64_t)h0 | ((uint64_t)h1 << 32)));
+}
+
 // x of lane l (l uniform across the wave).
 __device__ __forceinline__ uint32_t lane_read(uint32_t x, int l)
 {

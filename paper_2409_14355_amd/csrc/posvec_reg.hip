@@ -43,16 +43,43 @@ __device__ __forceinline__ double cand_score_r(double parent, double w, int k)
     return parent + w * (double)k;
 }
 
-// Compare-exchange of entry (cs, cp) with the entry of lane ^ s, keeping the
-// smaller key in the lower lane when `asc`, the larger otherwise.
-__device__ __forceinline__ void lane_stage(double &cs, uint32_t &cp, int s, bool asc)
+// Compare-exchange of entry (cs, cp) with the entry of lane ^ S, keeping the
+// smaller key in the lower lane when `asc`, the larger otherwise.  At
+// distance 16 or 32 one swap gives both entries of the pair and the lane's
+// side picks; below, the partner's entry comes from DPP.
+template <int S>
+__device__ __forceinline__ void lane_stage(double &cs, uint32_t &cp, bool asc)
 {
-    const double os = lane_xor_n(cs, s);
-    const uint32_t op = lane_xor_n(cp, s);
-    const bool lower = (threadIdx.x & (unsigned)s) == 0;
-    const bool take = (lower == asc) == key_lt(os, op, cs, cp);
-    cs = take ? os : cs;
-    cp = take ? op : cp;
+    if constexpr (S >= 16) {
+        double ls, hs;
+        uint32_t lp, hp;
+        lane_pair<S>(cs, ls, hs);
+        lane_pair<S>(cp, lp, hp);
+        const bool upper = (threadIdx.x & (unsigned)S) != 0;
+        const bool take_hi = (key_lt(hs, hp, ls, lp) != upper) == asc;
+        cs = take_hi ? hs : ls;
+        cp = take_hi ? hp : lp;
+    } else {
+        const double os = lane_xor_n(cs, S);
+        const uint32_t op = lane_xor_n(cp, S);
+        const bool lower = (threadIdx.x & (unsigned)S) == 0;
+        const bool take = (lower == asc) == key_lt(os, op, cs, cp);
+        cs = take ? os : cs;
+        cp = take ? op : cp;
+    }
+}
+
+// The same at a run-time distance (constant after unrolling).
+__device__ __forceinline__ void lane_stage_n(double &cs, uint32_t &cp, int s, bool asc)
+{
+    switch (s) {
+    case 1: lane_stage<1>(cs, cp, asc); break;
+    case 2: lane_stage<2>(cs, cp, asc); break;
+    case 4: lane_stage<4>(cs, cp, asc); break;
+    case 8: lane_stage<8>(cs, cp, asc); break;
+    case 16: lane_stage<16>(cs, cp, asc); break;
+    default: lane_stage<32>(cs, cp, asc); break;
+    }
 }
 
 // Inclusive prefix sum over the 64 lanes: four row shifts inside each row of
@@ -195,9 +222,12 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
             }
             Zs = cs[0];
             Zp = cp[0];
-#pragma unroll
-            for (int st = 32; st >= 1; st >>= 1)
-                lane_stage(Zs, Zp, st, true);
+            lane_stage<32>(Zs, Zp, true);
+            lane_stage<16>(Zs, Zp, true);
+            lane_stage<8>(Zs, Zp, true);
+            lane_stage<4>(Zs, Zp, true);
+            lane_stage<2>(Zs, Zp, true);
+            lane_stage<1>(Zs, Zp, true);
             if (g >= K) {
                 Zs = INF;
                 Zp = kSentinel;
@@ -306,7 +336,7 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
                     ks = take ? os : ks;
                     kr = take ? op : kr;
                 } else {
-                    lane_stage(ks, kr, stride, asc);
+                    lane_stage_n(ks, kr, stride, asc);
                 }
             }
         }
