@@ -233,13 +233,15 @@ __device__ __forceinline__ float nearest_level(float z, float &m)
 }
 
 // second closest level of one axis: the neighbour of the closest level m0
-// on the side of z, or the other neighbour at the edge of the constellation
+// on the side of z (dz = z - level of m0), or at the edge of the constellation
+// the other neighbour: m0 + s reflected back into 0 .. L-1 (exact small
+// integers; no compare and select)
 template <int L>
-__device__ __forceinline__ void axis_second(float z, float m0, float lv0, float &m1, float &e1)
+__device__ __forceinline__ void axis_second(float z, float dz, float m0, float &m1, float &e1)
 {
-    const float s = (z >= lv0) ? 1.f : -1.f;
-    const float a = m0 + s;
-    m1 = ((a >= 0.f) & (a <= (float)(L - 1))) ? a : m0 - s;
+    constexpr float top = (float)(L - 1);
+    const float s = __builtin_copysignf(1.f, dz);  // dz = +0 when z is on the level: upward, as z >= level
+    m1 = top - fabsf(top - fabsf(m0 + s));
     e1 = square_rn(z - level_of<L>(m1));
 }
 
@@ -318,8 +320,7 @@ __device__ __forceinline__ void kth_small(float zI, float zQ, int k, float &mI, 
 // path prefix share z, so one round usually serves all of them.  Must be
 // reached by every lane of the wave.
 template <int L>
-__device__ __forceinline__ void kth_wave(bool need, float zI, float zQ, int k, float &mI, float &mQ, float &eI,
-                                         float &eQ)
+__device__ __forceinline__ void kth_wave(bool need, float zI, float zQ, int k, float &mI, float &mQ, float &e)
 {
     constexpr int HB = Axis<L>::HB;
     constexpr int NPT = L * L;  // 16 or 64 points: sorted within rows of NPT lanes
@@ -356,8 +357,7 @@ __device__ __forceinline__ void kth_wave(bool need, float zI, float zQ, int k, f
         if (mine) {
             mI = (float)gray_decode(got >> HB);
             mQ = (float)gray_decode(got & (L - 1));
-            eI = square_rn(zI - level_of<L>(mI));
-            eQ = square_rn(zQ - level_of<L>(mQ));
+            e = square_rn(zI - level_of<L>(mI)) + square_rn(zQ - level_of<L>(mQ));
         }
         pend &= ~__ballot(mine);
     }
@@ -486,40 +486,38 @@ __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_
                 zQ = __builtin_amdgcn_fdot2_f32_bf16(r, __builtin_bit_cast(bf162_t, sb[e]), zQ, false);
             }
         }
-        float mI, mQ, eI, eQ;
+        float mI, mQ, e;  // the chosen point and its squared distance
         if (gzero != 0.f) {
             // R_ll = 0: every point is equally far; the k-th in index order
             const int idx = min(max(k - 1, 0), L * L - 1);
             mI = (float)gray_decode(idx >> Axis<L>::HB);
             mQ = (float)gray_decode(idx & (L - 1));
-            eI = square_rn(zI);
-            eQ = square_rn(zQ);
+            e = square_rn(zI) + square_rn(zQ);
         } else {
             const float lI = nearest_level<L>(zI, mI), lQ = nearest_level<L>(zQ, mQ);
             const float dI = zI - lI, dQ = zQ - lQ;
-            eI = square_rn(dI);
-            eQ = square_rn(dQ);
+            float eI = square_rn(dI), eQ = square_rn(dQ);
+            e = eI + eQ;
             if (FIRST) {
             } else if (k == 2) {
                 // rank 2 is (second I, closest Q) or (closest I, second Q):
                 // every other point is farther than one of the two
                 float mI1, eI1, mQ1, eQ1;
-                axis_second<L>(zI, mI, lI, mI1, eI1);
-                axis_second<L>(zQ, mQ, lQ, mQ1, eQ1);
-                if (eI1 + eQ <= eI + eQ1) {
-                    mI = mI1;
-                    eI = eI1;
-                } else {
-                    mQ = mQ1;
-                    eQ = eQ1;
-                }
+                axis_second<L>(zI, dI, mI, mI1, eI1);
+                axis_second<L>(zQ, dQ, mQ, mQ1, eQ1);
+                const float cI = eI1 + eQ, cQ = eI + eQ1;
+                const bool inI = cI <= cQ;
+                mI = inI ? mI1 : mI;
+                mQ = inI ? mQ : mQ1;
+                e = inI ? cI : cQ;
             } else if (k == 3 || k == 4) {
                 kth_small<L>(zI, zQ, k, mI, lI, eI, mQ, lQ, eQ);
+                e = eI + eQ;
             }
             if constexpr (L > 2 && !FIRST)
-                kth_wave<L>(k > 4, zI, zQ, k, mI, mQ, eI, eQ);
+                kth_wave<L>(k > 4, zI, zQ, k, mI, mQ, e);
         }
-        metric = fmaf(gw, eI + eQ, metric);
+        metric = fmaf(gw, e, metric);
         decf[d >> 2] = fmaf(fmaf(mQ, (float)L, mI), code_weight(d), decf[d >> 2]);
         if (d + 1 < N && __all(!live || metric > prune))
             break;
