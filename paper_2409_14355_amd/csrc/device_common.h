@@ -253,6 +253,23 @@ __device__ __forceinline__ void axis_second(float z, float dz, float m0, float &
 template <int L>
 __device__ __forceinline__ void axis_ranks3(float z, float m0, float lv0, float (&m)[3], float (&e)[3])
 {
+    if constexpr (L == 4) {
+        // Four levels: mirrored so that z lies at or above its closest level
+        // (m' = m0, or 3 - m0), ranks 1..3 are one of four rows, 2 bits a
+        // rank and 6 bits a row: m' = 0: 1 2 3; 1: 2 0 3; 2: 3 1 0; 3: 2 1 0.
+        // The same levels as the zig-zag below (exact small integers).
+        constexpr uint32_t kRows = 57u | (50u << 6) | (7u << 12) | (6u << 18);
+        const float s = __builtin_copysignf(1.f, z - lv0);  // +0 on the level: upward, as z >= level
+        const uint32_t row = kRows >> __umul24((uint32_t)fmaf(s, m0 - 1.5f, 1.5f), 6u);
+        const float c = fmaf(-1.5f, s, 1.5f);               // unmirror: m = s r + c
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const float mt = fmaf(s, (float)((row >> (2 * t)) & 3u), c);
+            m[t] = mt;
+            e[t] = square_rn(z - level_of<L>(mt));
+        }
+        return;
+    }
     const float s = (z >= lv0) ? 1.f : -1.f;
     const float cp = s > 0.f ? (float)(L - 1) - m0 : m0;  // levels on side +s
     const float cm = (float)(L - 1) - cp;                  // levels on side -s
