@@ -123,6 +123,11 @@ __device__ __forceinline__ void lane_pair(double x, double &lo, double &hi)
     hi = __longlong_as_double((long long)((uint64_t)h0 | ((uint64_t)h1 << 32)));
 }
 
+// Active lanes of the wave where c holds, as a lane mask.  A compare passed
+// straight in becomes the mask itself (HIP's __ballot and __all take an
+// int: a select and a compare more per vote).
+__device__ __forceinline__ uint64_t lane_mask(bool c) { return __builtin_amdgcn_ballot_w64(c); }
+
 // x of lane l (l uniform across the wave).
 __device__ __forceinline__ uint32_t lane_read(uint32_t x, int l)
 {
@@ -346,7 +351,7 @@ __device__ __forceinline__ void kth_wave(bool need, float zI, float zQ, int k, f
     const int cI = c & (L - 1), cQ = c >> HB;
     const int cidx = (gray_code(cI) << HB) | gray_code(cQ);
     const float vI = level_of<L>((float)cI), vQ = level_of<L>((float)cQ);
-    uint64_t pend = __ballot(need);
+    uint64_t pend = lane_mask(need);
     while (pend) {
         const int src = __builtin_ctzll(pend);
         const float zi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zI), src));
@@ -376,7 +381,7 @@ __device__ __forceinline__ void kth_wave(bool need, float zI, float zQ, int k, f
             mQ = (float)gray_decode(got & (L - 1));
             e = square_rn(zI - level_of<L>(mI)) + square_rn(zQ - level_of<L>(mQ));
         }
-        pend &= ~__ballot(mine);
+        pend &= ~lane_mask(mine);
     }
 }
 
@@ -463,14 +468,15 @@ struct RLanes {
 // decision, so the same bits), and a wavefront that stops early never
 // computes the rows below.  rl holds R' transposed: rl[d N + e] is the
 // coefficient of s_e in row d (lattice units of row d).  `prune`: the wave
-// stops once every lane with live = true has a metric above it (all lanes
-// must take part).  FIRST: every rank is 1 (path 0), the choice code for
+// stops once no lane with live = true has a metric at or below it (a NaN
+// metric counts as above; all lanes must take part).  FIRST: every rank is 1 (path 0), the choice code for
 // higher ranks is left out.
 template <int N, int L, int PREC, bool FIRST = false, typename YF, typename RF>
 __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_t *pw, float *decf, float prune,
                                          bool live)
 {
     float metric = 0.f;
+    const uint64_t live_lanes = lane_mask(live);
     float2 sv[N];                  // FP32: (s_I, s_Q) of the decided depths
     uint32_t sa[N], sb[N];         // FP16 / BF16: packed (-s_I, s_Q) and (-s_Q, -s_I)
 #pragma unroll
@@ -536,7 +542,7 @@ __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_
         }
         metric = fmaf(gw, e, metric);
         decf[d >> 2] = fmaf(fmaf(mQ, (float)L, mI), code_weight(d), decf[d >> 2]);
-        if (d + 1 < N && __all(!live || metric > prune))
+        if (d + 1 < N && (lane_mask(metric <= prune) & live_lanes) == 0)
             break;
         const float sI = level_of<L>(mI), sQ = level_of<L>(mQ);
         if constexpr (PREC == PREC_FP32) {
