@@ -55,9 +55,10 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t x)
     } else if constexpr (S == 2) {
         return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
     } else if constexpr (S == 4) {
-        const uint32_t from_up = (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x104, 0xF, 0xF, true);  // row_shl:4
-        const uint32_t from_dn = (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x114, 0xF, 0xF, true);  // row_shr:4
-        return (threadIdx.x & 4u) ? from_dn : from_up;
+        // row_shl:4 for every lane, then row_shr:4 written into banks 1 and 3
+        // only (the lanes with bit 2 set; the others keep the first move)
+        const int up = __builtin_amdgcn_mov_dpp(v, 0x104, 0xF, 0xF, true);
+        return (uint32_t)__builtin_amdgcn_update_dpp(up, v, 0x114, 0xF, 0xA, false);
     } else if constexpr (S == 8) {
         return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);  // row_ror:8
     } else if constexpr (S == 16) {
