@@ -685,9 +685,16 @@ __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cp
     }
 }
 
+// Occupancy of the path searches: eight wavefronts per SIMD (64 VGPRs).  The
+// descent is bound by the latency of its per-depth scalar loads of R and y
+// more than by VALU issue, so more resident wavefronts pay even where the
+// decided symbols of the deeper depths spill to scratch (16 users: 0.128 ->
+// 0.116 ms per 1200 x 14 launch; 24 users: 0.477 -> 0.352 ms per 3276 x 14).
+#define MPNL_PATH_OCCUPANCY __attribute__((amdgpu_waves_per_eu(8)))
+
 // grid: (S * T) x path groups; partials: (S * T, groups, 2 + (N + 3) / 4)
 template <int N, int L, int PREC>
-__global__ __launch_bounds__(256) void path_search_kernel(PathArgs a)
+__global__ __launch_bounds__(256) MPNL_PATH_OCCUPANCY void path_search_kernel(PathArgs a)
 {
     __shared__ float sm[4];
     __shared__ int sr[4];
@@ -852,7 +859,7 @@ struct MultiArgs {
 };
 
 template <int N, int L, int PREC>
-__global__ __launch_bounds__(256) void path_search_multi_kernel(MultiArgs a)
+__global__ __launch_bounds__(256) MPNL_PATH_OCCUPANCY void path_search_multi_kernel(MultiArgs a)
 {
     __shared__ float sm[4];
     __shared__ int sr[4];
