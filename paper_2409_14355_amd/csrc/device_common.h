@@ -690,7 +690,15 @@ __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cp
 // more than by VALU issue, so more resident wavefronts pay even where the
 // decided symbols of the deeper depths spill to scratch (16 users: 0.128 ->
 // 0.116 ms per 1200 x 14 launch; 24 users: 0.477 -> 0.352 ms per 3276 x 14).
+// The multi-job kernel carries more state: there only FP32 fits 64 VGPRs
+// well (FP16 at eight wavefronts: 40 cells 9.96 -> 11.7 ms), the reduced
+// precisions keep the registers they need (a minimum of one wavefront is no
+// constraint).
 #define MPNL_PATH_OCCUPANCY __attribute__((amdgpu_waves_per_eu(8)))
+template <int PREC>
+struct MultiOccupancy {
+    static constexpr int waves = PREC == PREC_FP32 ? 8 : 1;
+};
 
 // grid: (S * T) x path groups; partials: (S * T, groups, 2 + (N + 3) / 4)
 template <int N, int L, int PREC>
@@ -859,7 +867,8 @@ struct MultiArgs {
 };
 
 template <int N, int L, int PREC>
-__global__ __launch_bounds__(256) MPNL_PATH_OCCUPANCY void path_search_multi_kernel(MultiArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MultiOccupancy<PREC>::waves))) void
+path_search_multi_kernel(MultiArgs a)
 {
     __shared__ float sm[4];
     __shared__ int sr[4];
