@@ -427,7 +427,6 @@ __device__ __forceinline__ constexpr float code_weight(int d)
 // pruned path has a metric strictly above the minimum.
 constexpr float kBoundPad = 1.0001f;
 
-
 // Received values of one descent: yt of the vector in depth order, read
 // where each depth needs it, from a wave-uniform pointer (scalar loads) ...
 struct YUniform {
@@ -470,8 +469,8 @@ struct RLanes {
 // computes the rows below.  rl holds R' transposed: rl[d N + e] is the
 // coefficient of s_e in row d (lattice units of row d).  `prune`: the wave
 // stops once no lane with live = true has a metric at or below it (a NaN
-// metric counts as above; all lanes must take part).  FIRST: every rank is 1 (path 0), the choice code for
-// higher ranks is left out.
+// metric counts as above; all lanes must take part).  FIRST: every rank is 1
+// (path 0), the choice code for higher ranks is left out.
 template <int N, int L, int PREC, bool FIRST = false, typename YF, typename RF>
 __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_t *pw, float *decf, float prune,
                                          bool live)
@@ -694,7 +693,6 @@ __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cp
 // well (FP16 at eight wavefronts: 40 cells 9.96 -> 11.7 ms), the reduced
 // precisions keep the registers they need (a minimum of one wavefront is no
 // constraint).
-#define MPNL_PATH_OCCUPANCY __attribute__((amdgpu_waves_per_eu(8)))
 template <int PREC>
 struct MultiOccupancy {
     static constexpr int waves = PREC == PREC_FP32 ? 8 : 1;
@@ -702,7 +700,7 @@ struct MultiOccupancy {
 
 // grid: (S * T) x path groups; partials: (S * T, groups, 2 + (N + 3) / 4)
 template <int N, int L, int PREC>
-__global__ __launch_bounds__(256) MPNL_PATH_OCCUPANCY void path_search_kernel(PathArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void path_search_kernel(PathArgs a)
 {
     __shared__ float sm[4];
     __shared__ int sr[4];
