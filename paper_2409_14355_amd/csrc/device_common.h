@@ -690,12 +690,11 @@ __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cp
 // decided symbols of the deeper depths spill to scratch (16 users: 0.128 ->
 // 0.116 ms per 1200 x 14 launch; 24 users: 0.477 -> 0.352 ms per 3276 x 14).
 // The multi-job kernel carries more state: there only FP32 fits 64 VGPRs
-// well (FP16 at eight wavefronts: 40 cells 9.96 -> 11.7 ms), the reduced
-// precisions keep the registers they need (a minimum of one wavefront is no
-// constraint).
+// well; FP16 / BF16 run six wavefronts (80 VGPRs): 40 cells in FP16 take
+// 9.93 ms at their natural four to five, 9.84 at six, 11.7 at eight.
 template <int PREC>
 struct MultiOccupancy {
-    static constexpr int waves = PREC == PREC_FP32 ? 8 : 1;
+    static constexpr int waves = PREC == PREC_FP32 ? 8 : 6;
 };
 
 // grid: (S * T) x path groups; partials: (S * T, groups, 2 + (N + 3) / 4)
