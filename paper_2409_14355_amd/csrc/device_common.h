@@ -180,6 +180,7 @@ struct PosArgs {
     uint8_t *P;       // (S, K, NP)
     uint16_t *order;  // (S, K) path run by each lane, or null (identity)
     uint32_t *rec_g;  // (S, N, K) when the back pointers do not fit in LDS
+    uint16_t *rec16;  // (S, N, 256) back pointers of a 256-path set in global memory, or null (LDS)
 };
 
 // One job of a batched launch of a1 / a2 / a3 (slot state and workspace of

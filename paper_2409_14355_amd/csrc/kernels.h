@@ -24,6 +24,8 @@ struct SlotDev {
     uint8_t *P;            // (S, K, NP) ranks 1..|Q| per depth, padded with 1
     uint16_t *order;       // (S, K)     path run by each lane (K <= 256), else null
     uint32_t *rec;         // (S, N, K)  position-set back pointers when they do not fit in LDS
+    uint16_t *rec16;       // (S, N, 256) back pointers of a 256-path set in global memory when that
+                           //            saves a round of workgroups (posvec_reg_rec_global), else null
 };
 
 // Work item of the batched path search: one job (cell) of an uneven batch.
@@ -97,6 +99,10 @@ hipError_t launch_posvec_batch(const dev::StageJob *jobs, int n_jobs, int items,
                                hipStream_t st);
 hipError_t launch_rotate_batch(const dev::StageJob *jobs, int n_jobs, int items, hipStream_t st);
 size_t posvec_reg_lds_bytes(int N, int K);
+// Whether a slot's 256-path position set keeps its back pointers in global
+// memory (SlotDev::rec16): when, with cus compute units of lds_per_cu bytes of
+// LDS, that takes fewer rounds of workgroups than holding them in LDS.
+bool posvec_reg_rec_global(int S, int N, int K, int cus, size_t lds_per_cu);
 
 size_t posvec_lds_bytes(int N, int K, bool rec_in_lds);
 bool posvec_rec_fits_lds(int N, int K);

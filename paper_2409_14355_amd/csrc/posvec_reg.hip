@@ -21,6 +21,8 @@
 // (score, parent rank, k) compares as (score, packed).
 #include "device_common.h"
 
+#include <algorithm>
+
 namespace mpnl {
 namespace dev {
 namespace {
@@ -113,20 +115,24 @@ struct PosLds {
 // LDS of one workgroup: PosLds, then N * KP back pointers per depth, 16 bits
 // each (parent position | k << 8).  For 256 paths and N = 16 that is 24 KB,
 // so six workgroups fit a compute unit and a 1200-subcarrier slot runs in a
-// single round of workgroups.
-template <int E>
+// single round of workgroups.  REC_LDS = false: the back pointers live in
+// global memory (PosArgs::rec16) and the LDS holds PosLds only (16 KB for 256
+// paths, eight workgroups a compute unit), for slots where the larger count
+// saves a round (24 users: 28 KB, five a compute unit, 3276 subcarriers in
+// three rounds; without the pointers two).
+template <int E, bool REC_LDS = true>
 constexpr size_t pos_lds_bytes(int N)
 {
-    return sizeof(PosLds<E>) + (size_t)N * 64 * E * sizeof(uint16_t);
+    return sizeof(PosLds<E>) + (REC_LDS ? (size_t)N * 64 * E * sizeof(uint16_t) : 0);
 }
 
-template <int E>
+template <int E, bool REC_LDS = true>
 __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned char *smem)
 {
     constexpr int KP = 64 * E;
     constexpr double INF = (double)INFINITY;
     PosLds<E> &sh = *(PosLds<E> *)smem;
-    uint16_t *rec = (uint16_t *)(smem + sizeof(PosLds<E>));
+    uint16_t *rec = REC_LDS ? (uint16_t *)(smem + sizeof(PosLds<E>)) : a.rec16 + (size_t)s * a.N * KP;
     const int g = (int)threadIdx.x;  // list entry of this lane
     const int lane = g & 63, wv = g >> 6;
     const int K = a.K, N = a.N, nq = a.nq;
@@ -345,11 +351,11 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
     }
 }
 
-template <int E>
+template <int E, bool REC_LDS>
 __global__ __launch_bounds__(64 * E) void posvec_reg_kernel(PosArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    posvec_body<E>(a, blockIdx.x, smem);
+    posvec_body<E, REC_LDS>(a, blockIdx.x, smem);
 }
 
 // One launch for the position sets of many jobs (all with N_p <= 64 E and
@@ -369,6 +375,7 @@ __global__ __launch_bounds__(64 * E) void posvec_batch_kernel(const StageJob *jo
     a.NP = j.sd.NP;
     a.P = j.sd.P;
     a.rec_g = nullptr;
+    a.rec16 = nullptr;
     a.order = j.sd.order;
     posvec_body<E>(a, blockIdx.x - j.item_begin, smem);
 }
@@ -403,14 +410,34 @@ hipError_t launch_posvec_reg(const dev::PosArgs &a, hipStream_t st)
 {
     using namespace dev;
     if (a.K <= 64)
-        hipLaunchKernelGGL(posvec_reg_kernel<1>, dim3(a.S), dim3(64), pos_lds_bytes<1>(a.N), st, a);
+        hipLaunchKernelGGL((posvec_reg_kernel<1, true>), dim3(a.S), dim3(64), pos_lds_bytes<1>(a.N), st, a);
     else if (a.K <= 128)
-        hipLaunchKernelGGL(posvec_reg_kernel<2>, dim3(a.S), dim3(128), pos_lds_bytes<2>(a.N), st, a);
-    else if (a.K <= 256)
-        hipLaunchKernelGGL(posvec_reg_kernel<4>, dim3(a.S), dim3(256), pos_lds_bytes<4>(a.N), st, a);
+        hipLaunchKernelGGL((posvec_reg_kernel<2, true>), dim3(a.S), dim3(128), pos_lds_bytes<2>(a.N), st, a);
+    else if (a.K <= 256 && a.rec16 == nullptr)
+        hipLaunchKernelGGL((posvec_reg_kernel<4, true>), dim3(a.S), dim3(256), pos_lds_bytes<4>(a.N), st, a);
+    else if (a.K <= 256) {
+        const size_t lds = pos_lds_bytes<4, false>(a.N);
+        hipLaunchKernelGGL((posvec_reg_kernel<4, false>), dim3(a.S), dim3(256), lds, st, a);
+    }
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+bool posvec_reg_rec_global(int S, int N, int K, int cus, size_t lds_per_cu)
+{
+    using namespace dev;
+    if (K <= 128 || K > 256 || cus <= 0 || lds_per_cu == 0)
+        return false;
+    // workgroups of 4 wavefronts a compute unit: at most 8 (eight wavefronts
+    // a SIMD), fewer when the LDS runs out
+    const long with = std::min<long>(8, (long)(lds_per_cu / pos_lds_bytes<4>(N)));
+    const long without = std::min<long>(8, (long)(lds_per_cu / pos_lds_bytes<4, false>(N)));
+    if (with <= 0)
+        return without > 0;
+    const long rounds_with = (S + cus * with - 1) / (cus * with);
+    const long rounds_without = (S + cus * without - 1) / (cus * without);
+    return rounds_without < rounds_with;
 }
 
 }  // namespace mpnl

@@ -596,6 +596,7 @@ hipError_t launch_posvec(const SlotDev &sd, hipStream_t st)
     a.NP = sd.NP;
     a.P = sd.P;
     a.rec_g = sd.rec;
+    a.rec16 = sd.K <= 256 ? sd.rec16 : nullptr;
     a.order = sd.order;
     if (sd.K <= 256)
         return launch_posvec_reg(a, st);

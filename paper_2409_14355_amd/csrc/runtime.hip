@@ -47,6 +47,8 @@ struct mpnl_ctx {
     int last_hip = 0;
     int precision = MPNL_PREC_FP32;
     bool prune = true;  // stop path-search waves that can no longer win
+    int cus = 0;            // compute units and LDS bytes per compute unit of the device
+    size_t lds_per_cu = 0;  // (0: unknown; the position sets then keep everything in LDS)
     // second stream of one-shot detection: the rotation and the pruning
     // bounds run there while the position set runs on the caller's stream
     hipStream_t aux = nullptr;
@@ -286,10 +288,10 @@ const uint32_t *rq_of(const mpnl::SlotDev &sd, int precision)
 
 // Offsets of the slot arrays inside one pool block.
 struct SlotLayout {
-    size_t Qd, roff, rlat, rlat_h, rlat_b, diag, wd, permd, P, order, rec, total;
+    size_t Qd, roff, rlat, rlat_h, rlat_b, diag, wd, permd, P, order, rec, rec16, total;
 };
 
-SlotLayout slot_layout(int S, int M, int N, int K, int NP, bool rec_global)
+SlotLayout slot_layout(int S, int M, int N, int K, int NP, bool rec_global, bool rec16 = false)
 {
     SlotLayout L{};
     size_t o = 0;
@@ -309,6 +311,7 @@ SlotLayout slot_layout(int S, int M, int N, int K, int NP, bool rec_global)
     put(L.P, (size_t)S * K * NP);
     put(L.order, K <= 256 ? (size_t)S * K * sizeof(uint16_t) : 0);
     put(L.rec, rec_global ? (size_t)S * N * K * sizeof(uint32_t) : 0);
+    put(L.rec16, rec16 ? (size_t)S * N * 256 * sizeof(uint16_t) : 0);
     L.total = o;
     return L;
 }
@@ -340,7 +343,8 @@ size_t job_device_bytes(const mpnl_job &j)
         return 0;
     const int K = (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
     const int NP = (j.N + 3) / 4 * 4;
-    const SlotLayout L = slot_layout(j.S, j.M, j.N, K, NP, !posvec_rec_fits_lds(j.N, K));
+    // upper bound: a 256-path set may keep its back pointers in global memory
+    const SlotLayout L = slot_layout(j.S, j.M, j.N, K, NP, !posvec_rec_fits_lds(j.N, K), K > 128 && K <= 256);
     SlotDev sd{};
     sd.S = j.S;
     sd.N = j.N;
@@ -360,7 +364,8 @@ int prepare_impl(mpnl_ctx *ctx, const void *H, int S, int M, int N, int mod, int
     const int K = (int)std::min<long long>(n_paths, num_vectors_sat(1 << mod, N));
     const int NP = (N + 3) / 4 * 4;
     const bool rec_global = !mpnl::posvec_rec_fits_lds(N, K);
-    const SlotLayout L = slot_layout(S, M, N, K, NP, rec_global);
+    const bool rec16 = mpnl::posvec_reg_rec_global(S, N, K, ctx->cus, ctx->lds_per_cu);
+    const SlotLayout L = slot_layout(S, M, N, K, NP, rec_global, rec16);
     int blk = -1;
     int rc = pool_alloc(ctx, L.total, st, &blk);
     if (rc != MPNL_OK)
@@ -389,6 +394,7 @@ int prepare_impl(mpnl_ctx *ctx, const void *H, int S, int M, int N, int mod, int
     sd.P = (uint8_t *)(base + L.P);
     sd.order = K <= 256 ? (uint16_t *)(base + L.order) : nullptr;
     sd.rec = rec_global ? (uint32_t *)(base + L.rec) : nullptr;
+    sd.rec16 = rec16 ? (uint16_t *)(base + L.rec16) : nullptr;
     slot->block = blk;
     slot->stream = st;
     hipError_t e;
@@ -548,6 +554,13 @@ int mpnl_create(mpnl_ctx **ctx, int device, size_t hbm_budget_bytes, unsigned fl
     c->device = device;
     c->budget = hbm_budget_bytes;
     c->prune = (flags & MPNL_CREATE_NO_PRUNE) == 0;
+    int cus = 0, lds = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) == hipSuccess &&
+        cus > 0 && lds > 0) {
+        c->cus = cus;
+        c->lds_per_cu = (size_t)lds;
+    }
     *ctx = c;
     return MPNL_OK;
 }
@@ -1363,6 +1376,7 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
         sd.P = (uint8_t *)(b + L.P);
         sd.order = (uint16_t *)(b + L.order);
         sd.rec = nullptr;
+        sd.rec16 = nullptr;
         p->sd.push_back(sd);
         p->yt.push_back((float2 *)(dbase + ytoff[i]));
         p->bound.push_back(ctx->prune ? (float *)(dbase + boff[i]) : nullptr);

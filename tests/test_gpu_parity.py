@@ -104,6 +104,33 @@ def test_position_set_stage(ctx, S, M, N, bits, K):
         assert np.array_equal(P[s], Pr), (s, bmargin)
 
 
+def test_position_set_large_slot(ctx):
+    """A slot of 3276 subcarriers with 24 users and 256 paths, where the
+    position-set kernel keeps its back pointers in global memory (fewer rounds
+    of workgroups than with them in LDS on this device): the sets of sampled
+    subcarriers equal the oracle's entry for entry, and equal those of the
+    same subcarriers prepared in a small slot (back pointers in LDS)."""
+    S, M, N, bits, K = 3276, 24, 24, 4, 256
+    _say("posvec large slot", S, N, K)
+    sl = synth.make_slot(S=S, T=1, M=M, N=N, bits=bits, snr_db=18, seed=(203, S, N))
+    slot = ctx.slot_prepare(_dev(sl.H), bits, K)
+    ex = slot.export()
+    torch.cuda.synchronize()
+    w = ex["w"].cpu().numpy()
+    P = ex["P"].cpu().numpy()
+    slot.release()
+    sub = np.sort(np.random.default_rng(204).choice(S, size=24, replace=False))
+    small = ctx.slot_prepare(_dev(np.ascontiguousarray(sl.H[sub])), bits, K)
+    ex_small = small.export()
+    torch.cuda.synchronize()
+    P_small = ex_small["P"].cpu().numpy()
+    small.release()
+    assert np.array_equal(P[sub], P_small)
+    for i, s in enumerate(sub):
+        Pr, _, bmargin = oracle.position_set(w[s], 1 << bits, K)
+        assert np.array_equal(P[s], Pr), (int(s), bmargin)
+
+
 @pytest.mark.parametrize("M,N,bits,K", [(4, 4, 2, 200), (6, 6, 4, 256), (5, 5, 2, 64), (8, 8, 6, 1000)])
 def test_position_set_exact_ties(ctx, M, N, bits, K):
     """Identity channels give exactly equal weights (all 1.0) and zeroed
