@@ -317,7 +317,7 @@ int nmax_bucket(int N)
 
 size_t path_partial_bytes(const SlotDev &sd, int T)
 {
-    const int groups = (sd.K + 255) / 256;
+    const int groups = (sd.K + 63) / 64;
     if (groups <= 1)
         return 0;
     return (size_t)sd.S * T * groups * (2 + (sd.N + 3) / 4) * sizeof(float);
@@ -331,7 +331,7 @@ hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_
     PathArgs a = path_args(sd, yt, T, out);
     a.rq = precision == PREC_FP16 ? sd.rlat_h : precision == PREC_BF16 ? sd.rlat_b : nullptr;
     a.bound = bound;
-    const int groups = (sd.K + 255) / 256;
+    const int groups = (sd.K + 63) / 64;
     if (groups > 1) {
         if (part == nullptr)
             return hipErrorInvalidValue;
