@@ -341,7 +341,7 @@ hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_
     if (e != hipSuccess || groups <= 1)
         return e;
     const int vecs = sd.S * T;
-    const dim3 grid((vecs + 255) / 256), block(256);
+    const dim3 grid((vecs + 63) / 64), block(64);  // one lane a vector; many small workgroups spread the loads
     if (sd.bits == 2)
         hipLaunchKernelGGL(path_group_reduce_kernel<2>, grid, block, 0, st, a, groups);
     else if (sd.bits == 4)
