@@ -148,6 +148,33 @@ int mpnl_detect(mpnl_ctx *ctx, const void *H, const void *y, int S, int T,
                 int M, int N, int mod, int n_paths, int32_t *out,
                 void *stream);
 
+/* ---- allocation-free one-shot detection ------------------------------------ */
+
+/* Size of the device scratch area behind mpnl_detect_static(). */
+#define MPNL_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation.  The same
+   a1 .. a5 as mpnl_detect() on the same arguments, with the same result,
+   but every intermediate buffer (slot state, rotated vectors, pruning
+   record, path-group partials) lives in one fixed area of
+   MPNL_STATIC_SCRATCH_BYTES in device memory that the library holds on each
+   device it runs on until the process ends (located when the first context
+   on that device is created).  The stages run one after another on
+   `stream` (no second stream, no events), and the call neither allocates
+   nor frees device or host memory; the context's budget does not count the
+   area.  Every call on a device shares that device's area and leaves its
+   contents behind: calls that may overlap on one device (other streams,
+   other contexts or threads) race and give undefined results, so order them
+   on one stream.  About 100 MB covers a 24-user, 3276-subcarrier slot of 14
+   symbols with 256 paths; the need grows with S (M N + N N + K N) and
+   with T S N.  Errors: as mpnl_detect(); MPNL_E_NOMEM when the call's
+   buffers do not fit the area (nothing is enqueued); MPNL_E_HIP when the
+   area could not be located on the device (see mpnl_last_hip_error()). */
+int mpnl_detect_static(mpnl_ctx *ctx, const void *H, const void *y, int S,
+                       int T, int M, int N, int mod, int n_paths,
+                       int32_t *out, void *stream);
+
 /* ---- slot-resident state (serving) ---------------------------------------- */
 
 /* Run a1 (sorted QR) and a2 (position-vector set) for one slot's channel and

@@ -26,6 +26,7 @@ MPNL_E_HIP = -4
 MPNL_MAX_USERS = 32
 MPNL_MAX_ANTENNAS = 32
 MPNL_MAX_PATHS = 4096
+MPNL_STATIC_SCRATCH_BYTES = 128 << 20
 MPNL_QPSK, MPNL_QAM16, MPNL_QAM64 = 2, 4, 6
 MPNL_PREC_FP32, MPNL_PREC_FP16, MPNL_PREC_BF16 = 0, 1, 2
 
@@ -37,7 +38,7 @@ EXPORTED = (
     "mpnl_batch_create", "mpnl_batch_run", "mpnl_batch_info", "mpnl_batch_destroy",
     "mpnl_job_bytes", "mpnl_server_create", "mpnl_server_now_us", "mpnl_server_submit",
     "mpnl_server_poll", "mpnl_server_pending", "mpnl_server_run_poisson", "mpnl_server_destroy",
-    "mpnl_sched_simulate", "mpnl_mmse_detect", "mpnl_detect_regularized",
+    "mpnl_sched_simulate", "mpnl_mmse_detect", "mpnl_detect_regularized", "mpnl_detect_static",
 )
 MPNL_JOB_DONE, MPNL_JOB_REJECTED, MPNL_JOB_DROPPED, MPNL_JOB_FAILED = 0, 1, 2, 3
 MPNL_CREATE_NO_PRUNE = 1
@@ -103,6 +104,7 @@ def lib() -> ctypes.CDLL:
     L.mpnl_set_precision.argtypes = [vp, ip]
     L.mpnl_memory_usage.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     L.mpnl_detect.argtypes = [vp, vp, vp, ip, ip, ip, ip, ip, ip, vp, vp]
+    L.mpnl_detect_static.argtypes = [vp, vp, vp, ip, ip, ip, ip, ip, ip, vp, vp]
     L.mpnl_slot_prepare.argtypes = [vp, vp, ip, ip, ip, ip, ip, vp, ctypes.POINTER(vp)]
     L.mpnl_slot_detect.argtypes = [vp, vp, vp, ip, vp, vp]
     L.mpnl_slot_detect_soft.argtypes = [vp, vp, vp, ip, ctypes.c_float, ctypes.c_float, vp, vp, vp]
@@ -205,6 +207,12 @@ def mpnl_detect(ctx: int, H, y, S: int, T: int, M: int, N: int, mod: int, n_path
                 stream=None) -> None:
     _check(lib().mpnl_detect(ctx, _ptr(H), _ptr(y), S, T, M, N, mod, n_paths, _ptr(out),
                              _stream(stream)), "mpnl_detect")
+
+
+def mpnl_detect_static(ctx: int, H, y, S: int, T: int, M: int, N: int, mod: int, n_paths: int, out,
+                       stream=None) -> None:
+    _check(lib().mpnl_detect_static(ctx, _ptr(H), _ptr(y), S, T, M, N, mod, n_paths, _ptr(out),
+                                    _stream(stream)), "mpnl_detect_static")
 
 
 def mpnl_slot_prepare(ctx: int, H, S: int, M: int, N: int, mod: int, n_paths: int,
@@ -403,6 +411,15 @@ class Context:
         if out is None:
             out = torch.empty((T, S, N), dtype=torch.int32, device=H.device)
         mpnl_detect(self.handle, H, y, S, T, M, N, mod, n_paths, out, stream)
+        return out
+
+    def detect_static(self, H, y, mod: int, n_paths: int, out=None, stream=None):
+        """As detect(), with no device allocation (the library's static scratch area)."""
+        import torch
+        S, T, M, N = _shapes(H, y)
+        if out is None:
+            out = torch.empty((T, S, N), dtype=torch.int32, device=H.device)
+        mpnl_detect_static(self.handle, H, y, S, T, M, N, mod, n_paths, out, stream)
         return out
 
     def detect_regularized(self, H, y, mod: int, n_paths: int, sigma2: float, out=None, stream=None):

@@ -9,6 +9,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -34,6 +35,41 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 }  // namespace
 
+// Device scratch of the allocation-free detection (mpnl_detect_static): the
+// slot state, rotated vectors, pruning record and path-group partials of one
+// call.  Every device that loads the library holds its own copy until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address on each device comes from hipGetSymbolAddress (static_scratch_of).
+static __device__ __align__(256) unsigned char scratch[MPNL_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+bool g_scratch_done[kMaxDevices];
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (the caller has made it current).
+hipError_t static_scratch_of(int device, void **ptr)
+{
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void *p = nullptr;
+        g_scratch_err[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_ptr[device] = g_scratch_err[device] == hipSuccess ? p : nullptr;
+        g_scratch_done[device] = true;
+    }
+    *ptr = g_scratch_ptr[device];
+    return g_scratch_err[device];
+}
+
+}  // namespace
+
 struct mpnl_slot {
     mpnl::SlotDev sd{};
     int block = -1;
@@ -47,6 +83,8 @@ struct mpnl_ctx {
     int last_hip = 0;
     int precision = MPNL_PREC_FP32;
     bool prune = true;  // stop path-search waves that can no longer win
+    void *scratch = nullptr;       // device address of the static scratch on this device
+    int scratch_err = 0;           // hipError_t of its lookup at creation
     int cus = 0;            // compute units and LDS bytes per compute unit of the device
     size_t lds_per_cu = 0;  // (0: unknown; the position sets then keep everything in LDS)
     // second stream of one-shot detection: the rotation and the pruning
@@ -536,6 +574,60 @@ int oneshot_impl(mpnl_ctx *ctx, const void *H, const void *y, int S, int T, int 
     return e == hipSuccess ? MPNL_OK : hip_fail(ctx, e);
 }
 
+// One-shot a1..a5 with every intermediate buffer in the static scratch at
+// `base` (cap bytes): the stages run one after another on `st`; nothing is
+// allocated, no event is recorded and no second stream is used.
+int static_impl(mpnl_ctx *ctx, char *base, size_t cap, const void *H, const void *y, int S, int T, int M, int N,
+                int mod, int n_paths, int32_t *out, hipStream_t st)
+{
+    if ((long long)S * T > INT_MAX / 2)
+        return MPNL_E_UNSUPPORTED;
+    const int K = (int)std::min<long long>(n_paths, num_vectors_sat(1 << mod, N));
+    const int NP = (N + 3) / 4 * 4;
+    const bool rec_global = !mpnl::posvec_rec_fits_lds(N, K);
+    // back pointers of a 256-path set stay in LDS (rec16 off): the same set,
+    // less scratch
+    const SlotLayout L = slot_layout(S, M, N, K, NP, rec_global, false);
+    mpnl::SlotDev sd{};
+    sd.S = S;
+    sd.M = M;
+    sd.N = N;
+    sd.bits = mod;
+    sd.K = K;
+    sd.NP = NP;
+    const size_t yt_bytes = align_up((size_t)T * S * N * sizeof(float2));
+    const size_t part_bytes = align_up(mpnl::path_partial_bytes(sd, T));
+    const size_t bound_bytes = ctx->prune ? align_up(mpnl::bound_record_bytes(S, T, N)) : 0;
+    if (L.total + yt_bytes + part_bytes + bound_bytes > cap)
+        return MPNL_E_NOMEM;
+    sd.Qd = (float2 *)(base + L.Qd);
+    sd.roff = (float2 *)(base + L.roff);
+    sd.rlat = (float2 *)(base + L.rlat);
+    sd.rlat_h = (uint32_t *)(base + L.rlat_h);
+    sd.rlat_b = (uint32_t *)(base + L.rlat_b);
+    sd.diag = (float4 *)(base + L.diag);
+    sd.wd = (double *)(base + L.wd);
+    sd.permd = (int32_t *)(base + L.permd);
+    sd.P = (uint8_t *)(base + L.P);
+    sd.order = K <= 256 ? (uint16_t *)(base + L.order) : nullptr;
+    sd.rec = rec_global ? (uint32_t *)(base + L.rec) : nullptr;
+    sd.rec16 = nullptr;
+    char *work = base + L.total;
+    float2 *yt = (float2 *)work;
+    float *part = part_bytes ? (float *)(work + yt_bytes) : nullptr;
+    float *bound = bound_bytes ? (float *)(work + yt_bytes + part_bytes) : nullptr;
+    hipError_t e = mpnl::launch_sqrd((const float2 *)H, sd, st);
+    if (e == hipSuccess)
+        e = mpnl::launch_posvec(sd, st);
+    if (e == hipSuccess)
+        e = mpnl::launch_rotate(sd, (const float2 *)y, T, yt, st);
+    if (e == hipSuccess && bound)
+        e = mpnl::launch_path_bound(sd, yt, T, ctx->precision, bound, st);
+    if (e == hipSuccess)
+        e = mpnl::launch_path_search(sd, yt, T, out, ctx->precision, part, bound, st);
+    return e == hipSuccess ? MPNL_OK : hip_fail(ctx, e);
+}
+
 }  // namespace
 
 extern "C" {
@@ -560,6 +652,12 @@ int mpnl_create(mpnl_ctx **ctx, int device, size_t hbm_budget_bytes, unsigned fl
         cus > 0 && lds > 0) {
         c->cus = cus;
         c->lds_per_cu = (size_t)lds;
+    }
+    {
+        // the static scratch of mpnl_detect_static: located once per device,
+        // with that device current; a failure is reported by that call only
+        DeviceGuard g(device);
+        c->scratch_err = g.ok() ? (int)static_scratch_of(device, &c->scratch) : (int)hipErrorInvalidDevice;
     }
     *ctx = c;
     return MPNL_OK;
@@ -778,6 +876,25 @@ int mpnl_detect(mpnl_ctx *ctx, const void *H, const void *y, int S, int T, int M
     if (!g.ok())
         return hip_fail(ctx, hipErrorInvalidDevice);
     return oneshot_impl(ctx, H, y, S, T, M, N, mod, n_paths, out, (hipStream_t)stream);
+}
+
+int mpnl_detect_static(mpnl_ctx *ctx, const void *H, const void *y, int S, int T, int M, int N, int mod,
+                       int n_paths, int32_t *out, void *stream)
+{
+    if (!ctx || !H || !y || !out || T <= 0)
+        return MPNL_E_INVAL;
+    int rc = validate_shape(S, M, N, mod, n_paths);
+    if (rc != MPNL_OK)
+        return rc;
+    if (ctx->scratch_err != (int)hipSuccess || ctx->scratch == nullptr) {
+        ctx->last_hip = ctx->scratch_err ? ctx->scratch_err : (int)hipErrorInvalidSymbol;
+        return MPNL_E_HIP;
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok())
+        return hip_fail(ctx, hipErrorInvalidDevice);
+    return static_impl(ctx, (char *)ctx->scratch, MPNL_STATIC_SCRATCH_BYTES, H, y, S, T, M, N, mod, n_paths, out,
+                       (hipStream_t)stream);
 }
 
 int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *stream)
