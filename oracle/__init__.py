@@ -181,7 +181,9 @@ def position_set_brute(w_depth, nq: int, n_paths: int):
 
 
 def mpnl_vector(Q, R, perm, P, y, bits: int):
-    """One MPNL detection -> dict(idx, metric, kth_margin, metric_margin, metrics, paths)."""
+    """One MPNL detection -> dict(idx, metric, kth_margin, metric_margin, kth_margin_all,
+    metrics, paths).  kth_margin covers the paths that could still reach the
+    minimum; kth_margin_all every path (for outputs built from all paths)."""
     Q, R, y = _c128(Q), _c128(R), _c128(y)
     perm = np.ascontiguousarray(perm, dtype=np.int32)
     P = np.ascontiguousarray(P, dtype=np.uint8)
@@ -189,14 +191,14 @@ def mpnl_vector(Q, R, perm, P, y, bits: int):
     K = P.shape[0]
     out = np.zeros(N, np.int32)
     best = ctypes.c_double()
-    diag = np.full(4, np.inf)
+    diag = np.full(5, np.inf)
     mets = np.zeros(K, np.float64)
     paths = np.zeros((K, N), np.int32)
     _check(lib().orc_mpnl_vector(_ptr(Q), _ptr(R), _ptr(perm), _ptr(P), K, _ptr(y), M, N, bits,
                                  _ptr(out), ctypes.addressof(best), _ptr(diag), _ptr(mets),
                                  _ptr(paths)), "mpnl")
     return dict(idx=out, metric=best.value, kth_margin=diag[2], metric_margin=diag[3],
-                metrics=mets, paths=paths)
+                kth_margin_all=diag[4], metrics=mets, paths=paths)
 
 
 def zfsic(H, y, bits: int, perm) -> np.ndarray:

@@ -551,11 +551,23 @@ int orc_position_set_brute(const double *w_depth, int N, int nq, int n_paths,
 /*   3. keep the path with the smallest metric (equal: lowest r) and write */
 /*      its symbols back in original user order, out[perm[l]] = idx_l.     */
 /* diag (optional, 4 doubles): [0] unused here (pivot, filled by caller),  */
-/* [1] unused here (set boundary), [2] smallest relative gap between the   */
-/* chosen rank's distance and its neighbouring ranks over all paths and    */
-/* depths, [3] relative gap between the best and second-best path metric.  */
+/* [1] unused here (set boundary), [2] k-th-best margin: the smallest      */
+/* relative gap between the chosen rank's distance and its neighbouring    */
+/* ranks, over the (path, depth) pairs where a different choice could      */
+/* still change the result, [3] relative gap between the best and          */
+/* second-best path metric, [4] (if diag is given) the k-th-best margin   */
+/* over every (path, depth) pair, for outputs that use every path's metric */
+/* (soft output).                                                           */
+/* A k-th-best near-tie at depth d of path r can only matter when the      */
+/* partial metric of r through d is not already above the final minimum:   */
+/* the alternative path shares that partial metric (up to the tiny gap)   */
+/* and metrics only grow, so otherwise it can never win (KTH_REACH pads    */
+/* the comparison far beyond float32 rounding).  Depths with R_ll = 0 are */
+/* left out as well: every point ties there exactly and both the oracle    */
+/* and any implementation of the reading take them in index order.         */
 /* metrics_out (optional, K doubles): every path's metric.                 */
 /* ------------------------------------------------------------------------ */
+#define KTH_REACH 1e-3
 int orc_mpnl_vector(const cplx *Q, const cplx *R, const int32_t *perm,
                     const uint8_t *P, int K, const cplx *y, int M, int N,
                     int bits, int32_t *idx_out, double *best_metric,
@@ -574,6 +586,14 @@ int orc_mpnl_vector(const cplx *Q, const cplx *R, const int32_t *perm,
     }
     double best = INFINITY, second = INFINITY, kth_margin = INFINITY;
     int32_t best_idx[ORC_MAXN];
+    /* per (path, depth): the k-th-best gap and the partial metric through d */
+    double *gap = malloc(sizeof(double) * (size_t)K * N);
+    double *partial = malloc(sizeof(double) * (size_t)K * N);
+    if (!gap || !partial) {
+        free(gap);
+        free(partial);
+        return -1;
+    }
     for (int r = 0; r < K; r++) {
         cplx s[ORC_MAXN];
         int32_t sidx[ORC_MAXN];
@@ -601,19 +621,18 @@ int orc_mpnl_vector(const cplx *Q, const cplx *R, const int32_t *perm,
             }
             int k = P[(long)r * N + d] - 1;
             int c = order[k];
-            if (k > 0) {
-                double g = rel_gap(dist[order[k - 1]], dist[c]);
-                if (g < kth_margin)
-                    kth_margin = g;
-            }
-            if (k + 1 < nq) {
-                double g = rel_gap(dist[c], dist[order[k + 1]]);
-                if (g < kth_margin)
-                    kth_margin = g;
+            double gmin = INFINITY;
+            if (R[l * N + l] != 0) {
+                if (k > 0)
+                    gmin = fmin(gmin, rel_gap(dist[order[k - 1]], dist[c]));
+                if (k + 1 < nq)
+                    gmin = fmin(gmin, rel_gap(dist[c], dist[order[k + 1]]));
             }
             s[l] = pts[c];
             sidx[l] = c;
             metric += dist[c];
+            gap[(long)r * N + d] = gmin;
+            partial[(long)r * N + d] = metric;
         }
         if (metrics_out)
             metrics_out[r] = metric;
@@ -628,6 +647,15 @@ int orc_mpnl_vector(const cplx *Q, const cplx *R, const int32_t *perm,
             second = metric;
         }
     }
+    double kth_all = INFINITY;
+    for (long i = 0; i < (long)K * N; i++) {
+        if (partial[i] <= best * (1.0 + KTH_REACH) && gap[i] < kth_margin)
+            kth_margin = gap[i];
+        if (gap[i] < kth_all)
+            kth_all = gap[i];
+    }
+    free(gap);
+    free(partial);
     for (int l = 0; l < N; l++)
         idx_out[perm[l]] = best_idx[l];
     if (best_metric)
@@ -635,6 +663,7 @@ int orc_mpnl_vector(const cplx *Q, const cplx *R, const int32_t *perm,
     if (diag) {
         diag[2] = kth_margin;
         diag[3] = (K > 1) ? rel_gap(best, second) : INFINITY;
+        diag[4] = kth_all;
     }
     return 0;
 }
@@ -769,7 +798,7 @@ int orc_detect_slot(int method, const cplx *H, const cplx *y, int S, int T,
         for (int t = 0; t < T; t++) {
             const cplx *yv = y + ((long)t * S + s) * M;
             int32_t *o = out + ((long)t * S + s) * N;
-            double dv[4] = {pivot_margin, boundary, INFINITY, INFINITY};
+            double dv[5] = {pivot_margin, boundary, INFINITY, INFINITY, INFINITY};
             int rc = 0;
             switch (method) {
             case 0:
@@ -795,7 +824,7 @@ int orc_detect_slot(int method, const cplx *H, const cplx *y, int S, int T,
                 failed = 1;
             }
             if (diag)
-                memcpy(diag + ((long)t * S + s) * 4, dv, sizeof(dv));
+                memcpy(diag + ((long)t * S + s) * 4, dv, 4 * sizeof(double));
         }
         free(P);
         free(Q);

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from parity_util import classify
+from parity_util import check
 
 pytestmark = pytest.mark.gpu
 
@@ -77,8 +77,7 @@ def test_plan_replays_equal_alone(ctx, autotune):
         sl, got = slots[1], jobs[1]["out"].cpu().numpy()
         ref, diag = oracle.detect_slot("mpnl", sl.H, sl.y, sl.bits, n_paths=SMALL[1][5],
                                        want_diag=True, nthreads=8)
-        n_bad, counts, unexplained = classify(sl.H, sl.y, got, ref, diag, sl.bits)
-        assert not unexplained, unexplained[:3]
+        check(sl.H, sl.y, got, ref, diag, sl.bits, label="plan job 1")
     finally:
         plan.close()
 
@@ -151,8 +150,7 @@ def test_plan_forty_cells_full_size(ctx):
             got = jobs[i]["out"].cpu().numpy()[:, sub]
             ref, diag = oracle.detect_slot("mpnl", ss.H, ss.y, ss.bits, n_paths=K, want_diag=True,
                                            nthreads=8)
-            n_bad, counts, unexplained = classify(ss.H, ss.y, got, ref, diag, ss.bits)
-            assert not unexplained, (i, unexplained[:3])
+            check(ss.H, ss.y, got, ref, diag, ss.bits, label=f"cell {i} sample")
     finally:
         plan.close()
 

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from parity_util import TOL, classify
+from parity_util import TOL, check
 
 pytestmark = pytest.mark.gpu
 
@@ -46,10 +46,7 @@ def _run(ctx, sl, n_paths):
 def _assert_parity(sl, got, n_paths, nthreads=8, label=""):
     ref, diag = oracle.detect_slot("mpnl", sl.H, sl.y, sl.bits, n_paths=n_paths,
                                    want_diag=True, nthreads=nthreads)
-    n_bad, counts, unexplained = classify(sl.H, sl.y, got, ref, diag, sl.bits)
-    print(f"{label}: {n_bad} of {ref.shape[0] * ref.shape[1]} vectors differ; classes {counts}",
-          flush=True)
-    assert not unexplained, unexplained[:3]
+    n_bad, _ = check(sl.H, sl.y, got, ref, diag, sl.bits, label=label)
     return ref, n_bad
 
 
@@ -213,7 +210,13 @@ def test_zero_column_channel(ctx):
     sl.y[...] = np.einsum("smn,tsn->tsm", sl.H.astype(np.complex128),
                           synth._tx_points(4)[sl.s_idx]).astype(np.complex64) + sl.y * 0.01
     got = _run(ctx, sl, 64)
-    _assert_parity(sl, got, 64, label="zero-column")
+    # every point ties at the zero column's depth and paths that differ only
+    # there tie in metric: both sides take index order and the lowest path,
+    # so no vector may differ at all
+    ref = oracle.detect_slot("mpnl", sl.H, sl.y, sl.bits, n_paths=64, nthreads=8)
+    n_bad = int(np.any(got != ref, axis=-1).sum())
+    print(f"zero-column: {n_bad} of {got.shape[0] * got.shape[1]} vectors differ", flush=True)
+    assert n_bad == 0
     assert np.all(got[:, :, 2] == 0)
 
 
@@ -401,17 +404,21 @@ def test_soft_output_matches_oracle(ctx, snr, K, bits):
     llr = llr.cpu().numpy()
     got = out.cpu().numpy()
     ref, diag = oracle.detect_slot("mpnl", sl.H, sl.y, bits, n_paths=K, want_diag=True)
-    n_bad, _, unexplained = classify(sl.H, sl.y, got, ref, diag, bits)
-    assert not unexplained
+    check(sl.H, sl.y, got, ref, diag, bits, label=f"soft {snr} dB")
+    n_skip = 0
     for s in range(S):
         Q, R, perm, _ = oracle.sqrd(sl.H[s])
         P, _, _ = oracle.position_set(oracle.depth_weights(R), 1 << bits, K)
         for t in range(T):
             r = oracle.mpnl_vector(Q, R, perm, P, sl.y[t, s], bits)
             ol = oracle.llr_from_paths(r["metrics"], r["paths"], bits, sl.sigma2, 50.0)
-            if r["kth_margin"] < TOL:
+            # every path's metric enters the LLRs: a near-tie on any path counts
+            if r["kth_margin_all"] < TOL:
+                n_skip += 1
                 continue
             assert np.allclose(llr[t, s], ol, rtol=1e-3, atol=2e-3 * max(1.0, np.abs(ol).max())), (t, s)
+    print(f"soft {snr} dB: {n_skip} of {S * T} vectors skipped for a near-tie on some path", flush=True)
+    assert n_skip <= max(1, 0.05 * S * T)
 
 
 @pytest.mark.parametrize("shape", [(400, 14, 16, 16, 4, 256, 16.0, "iid"), (300, 14, 24, 24, 4, 256, 18.0, "kron"),

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from parity_util import classify
+from parity_util import check
 
 pytestmark = pytest.mark.gpu
 
@@ -52,9 +52,7 @@ def test_regularized_matches_oracle(ctx, case):
     got = got.cpu().numpy()
     Hx, yx = oracle.regularized_system(sl.H, sl.y, float(np.sqrt(np.float32(sl.sigma2))))
     ref, diag = oracle.detect_slot("mpnl", Hx, yx, bits, n_paths=K, want_diag=True, nthreads=8)
-    n_bad, counts, unexplained = classify(Hx, yx, got, ref, diag, bits)
-    print(f"{case}: {n_bad} of {S * T} vectors differ; classes {counts}", flush=True)
-    assert not unexplained, unexplained[:3]
+    check(Hx, yx, got, ref, diag, bits, label=str(case))
     ber_reg = synth.bit_errors(got, sl.s_idx, bits) / (sl.s_idx.size * bits)
     print("BER", ber_reg, flush=True)
 
