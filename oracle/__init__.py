@@ -7,6 +7,8 @@ NumPy arrays.  It shares no code with the HIP library.
 
 Parity status of each function (what pins it is in ``tests/test_oracle_*``):
   ml              pinned (two independent evaluations, closed forms)
+  sphere          pinned (= exhaustive ML on every vector of small systems,
+                  never above any other detector's metric at 16 users)
   zf, mmse        pinned (direct solve, special cases)
   sqrd            pinned (orthonormality, reconstruction, greedy property)
   position_set    pinned (brute-force sort on tiny sizes)
@@ -26,7 +28,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mpnl_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-METHOD = {"mpnl": 0, "ml": 1, "zf": 2, "mmse": 3, "zfsic": 4}
+METHOD = {"mpnl": 0, "ml": 1, "zf": 2, "mmse": 3, "zfsic": 4, "sphere": 5}
 
 
 def build(force: bool = False) -> str:
@@ -67,6 +69,7 @@ def lib():
         L.orc_position_set_brute.argtypes = [vp, ip, ip, ip, vp, vp]
         L.orc_mpnl_vector.argtypes = [vp, vp, vp, vp, ip, vp, ip, ip, ip, vp, vp, vp, vp, vp]
         L.orc_zfsic_vector.argtypes = [vp, vp, ip, ip, ip, vp, vp]
+        L.orc_sphere_vector.argtypes = [vp, vp, vp, vp, ip, ip, ip, ctypes.c_long, vp, vp, vp]
         L.orc_llr_from_paths.argtypes = [vp, vp, ip, ip, ip, dp, dp, vp]
         L.orc_detect_slot.argtypes = [ip, vp, vp, ip, ip, ip, ip, ip, ip, dp, vp, vp, ip]
         _lib = L
@@ -199,6 +202,20 @@ def mpnl_vector(Q, R, perm, P, y, bits: int):
                                  _ptr(paths)), "mpnl")
     return dict(idx=out, metric=best.value, kth_margin=diag[2], metric_margin=diag[3],
                 kth_margin_all=diag[4], metrics=mets, paths=paths)
+
+
+def sphere(H, y, bits: int, max_nodes: int = 200_000_000):
+    """Exact ML by sphere decoding on the sorted QR of H.
+    -> dict(idx (N,) int32, metric (QR form), nodes visited)."""
+    H, y = _c128(H), _c128(y)
+    M, N = H.shape
+    Q, R, perm, _ = sqrd(H)
+    out = np.zeros(N, np.int32)
+    met = ctypes.c_double()
+    nodes = ctypes.c_long()
+    _check(lib().orc_sphere_vector(_ptr(Q), _ptr(R), _ptr(perm), _ptr(y), M, N, bits, int(max_nodes), _ptr(out),
+                                   ctypes.addressof(met), ctypes.addressof(nodes)), "sphere")
+    return dict(idx=out, metric=met.value, nodes=nodes.value)
 
 
 def zfsic(H, y, bits: int, perm) -> np.ndarray:

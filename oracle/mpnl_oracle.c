@@ -271,8 +271,8 @@ int orc_mmse_vector(const cplx *H, const cplx *y, int M, int N, int bits,
 }
 
 /* ------------------------------------------------------------------------ */
-/* O4: sorted QR decomposition.  The paper's pre-processing "observes the    */
-/* MIMO channel before any transmission begins" (Sec. II); the reading      */
+/* O4: sorted QR decomposition.  The paper's pre-processing looks at the    */
+/* channel alone, ahead of any data (Sec. II); the reading                  */
 /* taken is the sorted QR of Wuebben et al. (2001): modified Gram-Schmidt   */
 /* where step i takes, among the columns not yet placed, the one with the   */
 /* smallest residual norm (equal norms: smaller original column index).     */
@@ -359,8 +359,8 @@ int orc_sqrd(const cplx *H, int M, int N, cplx *Q, cplx *R, int32_t *perm,
 }
 
 /* ------------------------------------------------------------------------ */
-/* O5: the set of position vectors.  The paper identifies "the relative     */
-/* position of the most promising solutions" from the channel alone,        */
+/* O5: the set of position vectors.  The paper fixes where the best        */
+/* candidate solutions lie relative to one another from the channel alone, */
 /* before transmission (Sec. II).  Reading taken: depth d detects row       */
 /* l = N-1-d of R; a position vector p (p_d in 1..|Q|) asks for the p_d-th  */
 /* closest symbol at depth d; its cost is                                   */
@@ -718,6 +718,115 @@ int orc_zfsic_vector(const cplx *H, const cplx *y, int M, int N, int bits,
 }
 
 /* ------------------------------------------------------------------------ */
+/* O1b: exact maximum-likelihood detection by sphere decoding, the classic  */
+/* non-linear detector the paper contrasts MPNL with (Sec. I): a depth-     */
+/* first tree search with Schnorr-Euchner enumeration (C. P. Schnorr and   */
+/* M. Euchner, Math. Programming 66, 1994; for MIMO detection see E. Agrell */
+/* et al., IEEE Trans. IT 48(8), 2002).  It reaches the ML result where     */
+/* enumerating Q^N is impossible (16 users, 16-QAM).                        */
+/* On the QR form of the channel (Q, R, perm from O4),                      */
+/*   ||y - H s||^2 = sum_l |yt_l - sum_{j>=l} R_{l,j} s'_j|^2 + const,      */
+/* yt = Q^H y, s' = s in the column order perm, the search assigns levels   */
+/* l = N-1 down to 0.  At a node the points of level l are taken in order  */
+/* of increasing |b - R_{l,l} c|^2, b = yt_l - sum_{j>l} R_{l,j} s'_j      */
+/* (equal distances: lower index), and a child is entered only while the   */
+/* partial metric stays below the best complete metric found so far; that */
+/* radius starts infinite, so the first leaf reached is the ordered        */
+/* ZF-SIC decision.  Since partial metrics only grow along a branch and    */
+/* the points of a node are visited in increasing distance, the first     */
+/* point that fails the test ends the node.  Every vector with a metric    */
+/* below the final radius is thus visited: the result minimises            */
+/* ||y - H s||^2 (among equal metrics, which have probability zero with    */
+/* continuous noise, the first leaf found is kept).  max_nodes bounds the  */
+/* work (visited nodes); -2 when it is exceeded.  metric_out: the QR-form  */
+/* metric sum_l |...|^2 of the result (||y - H s||^2 minus ||y||^2 -       */
+/* ||yt||^2).                                                              */
+/* ------------------------------------------------------------------------ */
+int orc_sphere_vector(const cplx *Q, const cplx *R, const int32_t *perm,
+                      const cplx *y, int M, int N, int bits, long max_nodes,
+                      int32_t *idx_out, double *metric_out, long *nodes_out)
+{
+    cplx pts[ORC_MAXQ];
+    int nq = orc_constellation(bits, pts);
+    if (nq < 0 || N < 1 || N > ORC_MAXN)
+        return -1;
+    cplx yt[ORC_MAXN];
+    for (int l = 0; l < N; l++) {
+        cplx a = 0;
+        for (int m = 0; m < M; m++)
+            a += conj(Q[m * N + l]) * y[m];
+        yt[l] = a;
+    }
+    int order[ORC_MAXN][ORC_MAXQ];
+    double dist[ORC_MAXN][ORC_MAXQ];
+    int next[ORC_MAXN];        /* next position in order[l] to try        */
+    double above[ORC_MAXN + 1]; /* partial metric of the levels above l    */
+    cplx s[ORC_MAXN];
+    int32_t sidx[ORC_MAXN], best_idx[ORC_MAXN];
+    double best = INFINITY;
+    long nodes = 0;
+    int l = N - 1;
+    above[N] = 0.0;
+    int enter = 1;
+    for (;;) {
+        if (enter) {
+            /* distances of every point at level l given the levels above */
+            cplx b = yt[l];
+            for (int j = l + 1; j < N; j++)
+                b -= R[l * N + j] * s[j];
+            for (int c = 0; c < nq; c++) {
+                dist[l][c] = abs2(b - R[l * N + l] * pts[c]);
+                order[l][c] = c;
+            }
+            for (int a = 1; a < nq; a++) { /* insertion sort by (distance, index) */
+                int v = order[l][a], z = a;
+                while (z > 0 && (dist[l][order[l][z - 1]] > dist[l][v] ||
+                                 (dist[l][order[l][z - 1]] == dist[l][v] && order[l][z - 1] > v))) {
+                    order[l][z] = order[l][z - 1];
+                    z--;
+                }
+                order[l][z] = v;
+            }
+            next[l] = 0;
+            enter = 0;
+        }
+        int moved = 0;
+        if (next[l] < nq) {
+            int c = order[l][next[l]];
+            double m = above[l + 1] + dist[l][c];
+            if (m < best) {
+                next[l]++;
+                s[l] = pts[c];
+                sidx[l] = c;
+                if (++nodes > max_nodes)
+                    return -2;
+                if (l == 0) {
+                    best = m;
+                    memcpy(best_idx, sidx, sizeof(int32_t) * N);
+                } else {
+                    above[l] = m;
+                    l--;
+                    enter = 1;
+                }
+                moved = 1;
+            }
+        }
+        if (!moved) { /* node exhausted or pruned: back to the level above */
+            l++;
+            if (l == N)
+                break;
+        }
+    }
+    for (int k = 0; k < N; k++)
+        idx_out[perm[k]] = best_idx[k];
+    if (metric_out)
+        *metric_out = best;
+    if (nodes_out)
+        *nodes_out = nodes;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Max-log soft output from the MPNL path list (the paper measures packet  */
 /* errors after LDPC decoding, Sec. III-B, which consumes per-bit soft     */
 /* values).  For bit b of user u:                                          */
@@ -764,6 +873,9 @@ int orc_llr_from_paths(const double *metrics, const int32_t *paths, int K,
 /* method: 0 = MPNL, 1 = ML, 2 = ZF, 3 = MMSE, 4 = ZF-SIC (SQRD order).     */
 /* diag (optional): (T, S, 4) doubles [pivot, boundary, kth, metric].      */
 /* ------------------------------------------------------------------------ */
+/* work bound of one sphere-decoded vector in the slot driver */
+#define ORC_SPHERE_MAX_NODES 200000000L
+
 int orc_detect_slot(int method, const cplx *H, const cplx *y, int S, int T,
                     int M, int N, int bits, int n_paths, double sigma2,
                     int32_t *out, double *diag, int nthreads)
@@ -781,7 +893,7 @@ int orc_detect_slot(int method, const cplx *H, const cplx *y, int S, int T,
         double pivot_margin = INFINITY, boundary = INFINITY;
         uint8_t *P = NULL;
         int K = 0;
-        if (method == 0 || method == 4) {
+        if (method == 0 || method == 4 || method == 5) {
             orc_sqrd(Hs, M, N, Q, R, perm, &pivot_margin);
         }
         if (method == 0) {
@@ -815,6 +927,9 @@ int orc_detect_slot(int method, const cplx *H, const cplx *y, int S, int T,
                 break;
             case 4:
                 rc = orc_zfsic_vector(Hs, yv, M, N, bits, perm, o);
+                break;
+            case 5:
+                rc = orc_sphere_vector(Q, R, perm, yv, M, N, bits, ORC_SPHERE_MAX_NODES, o, NULL, NULL);
                 break;
             default:
                 rc = -1;
