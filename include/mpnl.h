@@ -90,7 +90,10 @@ typedef struct mpnl_slot mpnl_slot;
    metric above the metric of path 0 (computed first), since the metric only
    grows along a path; the detected symbols are the same either way. */
 
-/* Create a context on HIP device `device`.  `hbm_budget_bytes` caps the
+/* A context is one device's share of the pooled detection resources that
+   Sec. II-A describes (a distributed unit serving several radio units): it
+   owns the device memory of the slots and workspace it runs, under a budget.
+   Create a context on HIP device `device`.  `hbm_budget_bytes` caps the
    device memory the context may hold for slot state and workspace (0 = no
    cap).  `flags`: 0 or MPNL_CREATE_NO_PRUNE.  On success *ctx receives the
    context.  Errors: MPNL_E_INVAL (ctx NULL, unknown flags), MPNL_E_HIP (bad
@@ -139,9 +142,12 @@ int mpnl_profile_collect(mpnl_ctx *ctx, double *total_ms, int *launches);
 
 /* ---- one-shot detection (a1 .. a5) --------------------------------------- */
 
-/* Detect T*S received vectors that share one channel per subcarrier
-   (a slot).  n_paths (N_p) is clamped to min(n_paths, |Q|^N); with the
-   clamp reached the result is exact maximum-likelihood detection.
+/* MPNL detection, Sec. II (the MPNL paragraph): the channel-only steps a1
+   and a2 followed by the per-vector steps a3 .. a5 (readings at the top of
+   this file).  Detect T*S received vectors that share one channel per
+   subcarrier (a slot; Sec. III-B: 14 OFDM symbols share a slot).  n_paths
+   (N_p) is clamped to min(n_paths, |Q|^N); with the clamp reached the
+   result is exact maximum-likelihood detection.
    Errors: MPNL_E_INVAL, MPNL_E_UNSUPPORTED (N > M, N > 32, M > 32,
    unknown mod, clamped N_p > MPNL_MAX_PATHS), MPNL_E_NOMEM, MPNL_E_HIP. */
 int mpnl_detect(mpnl_ctx *ctx, const void *H, const void *y, int S, int T,
@@ -177,22 +183,28 @@ int mpnl_detect_static(mpnl_ctx *ctx, const void *H, const void *y, int S,
 
 /* ---- slot-resident state (serving) ---------------------------------------- */
 
-/* Run a1 (sorted QR) and a2 (position-vector set) for one slot's channel and
-   keep Q, R, perm and the position vectors on the device until
+/* The part of MPNL that needs only the channel (Sec. II: the positions of
+   the most promising candidates are fixed from the channel before any data
+   arrives): a1 (sorted QR) and a2 (position-vector set) for one slot's
+   channel; Q, R, perm and the position vectors stay on the device until
    mpnl_slot_release().  The channel is only read by the enqueued work.
    On success *slot receives a handle owned by the context.
    Errors as mpnl_detect(). */
 int mpnl_slot_prepare(mpnl_ctx *ctx, const void *H, int S, int M, int N,
                       int mod, int n_paths, void *stream, mpnl_slot **slot);
 
-/* Run a3 .. a5 for T symbols of a prepared slot: y (T, S, M) -> out (T, S, N).
+/* The per-transmission part of MPNL (Sec. II: the candidates are formed and
+   evaluated in parallel, the best is the result): a3 .. a5 for T symbols of
+   a prepared slot, y (T, S, M) -> out (T, S, N).
    May be called any number of times on any stream; work on a stream other
    than the prepare stream must be ordered after it by the caller.
    Errors: MPNL_E_INVAL (null, T <= 0), MPNL_E_NOMEM, MPNL_E_HIP. */
 int mpnl_slot_detect(mpnl_ctx *ctx, mpnl_slot *slot, const void *y, int T,
                      int32_t *out, void *stream);
 
-/* As mpnl_slot_detect(), plus max-log soft output from the path list: for
+/* Soft input for the channel decoder behind detection (Sec. III-B decodes
+   with LDPC before measuring PER).  As mpnl_slot_detect(), plus max-log
+   soft output from the path list: for
    bit k of user u, llr = (min metric over paths whose symbol has bit k = 1
    minus min metric over paths with bit k = 0) / sigma2, positive favouring
    0, clipped to [-clip, clip] and set to +-clip when one hypothesis has no
@@ -234,11 +246,15 @@ typedef struct mpnl_job {
     int n_paths;
 } mpnl_job;
 
-/* Detect several independent jobs (cells) of different shapes: the sorted
+/* Pooled processing of several cells on one device (Sec. II-A: one
+   distributed unit serves the traffic of many radio units, and processing
+   goes where the traffic is).  Detect several independent jobs (cells) of
+   different shapes with the steps of mpnl_detect(): the sorted
    QR, position sets and rotation run per job, then the path searches of all
-   jobs with the same user count, modulation and workgroup size run in one
-   launch over their (job, subcarrier, symbol) work items; a job with more
-   than 256 paths runs its own path search.  Each job's result is identical
+   jobs with the same user count, modulation and paths rounded up to a
+   wavefront run in one launch, each received vector's paths split into
+   one-wavefront path groups whose best a second kernel reduces; a job with
+   more than 256 paths runs its own path search.  Each job's result is identical
    to mpnl_detect() on it alone, in the context's precision.  Errors: as
    mpnl_detect() for any job (shape errors are found before anything is
    enqueued); MPNL_E_NOMEM / MPNL_E_HIP may leave earlier jobs done. */
@@ -280,11 +296,18 @@ typedef struct mpnl_batch mpnl_batch;
 
 /* flags of mpnl_batch_create */
 #define MPNL_BATCH_AUTOTUNE 1u  /* on the first run, time the candidate
-                                   shapes (1, 2 or 4 received vectors per
-                                   workgroup) of every path-search launch and
-                                   keep the fastest before capturing         */
+                                   shapes of every path-search launch (path
+                                   groups of one wavefront or of the whole
+                                   vector, group- or vector-major order,
+                                   times 1, 2 or 4 work items per workgroup)
+                                   and keep the fastest before capturing;
+                                   without it every launch runs
+                                   one-wavefront groups, group major, four
+                                   per workgroup                            */
 
-/* Plan an uneven multi-cell batch whose job shapes (S, T, M, N, mod, n_paths;
+/* Pooled processing as mpnl_detect_batch() (Sec. II-A) for a set of cells
+   whose shapes repeat from slot to slot.  Plan an uneven multi-cell batch
+   whose job shapes (S, T, M, N, mod, n_paths;
    the pointers are ignored) stay fixed across runs.  Allocates every job's
    slot state and workspace once from the context budget and groups the jobs
    into batched launches: sorted QR per antenna-count bucket, position sets
@@ -308,9 +331,12 @@ int mpnl_batch_run(mpnl_ctx *ctx, mpnl_batch *batch, const mpnl_job *jobs,
                    void *stream);
 
 /* Launch shapes of the batch's path-search launches: n_launches receives
-   their number; shapes (room for max launches, 5 ints each) receives per
-   launch {N, mod, lanes per received vector, received vectors per
-   workgroup, workgroups}.  Errors: MPNL_E_INVAL for a null batch or a
+   their number; shapes (room for max launches, 7 ints each) receives per
+   launch {N, mod, lanes per received vector (paths rounded up to 64), lanes
+   per path group (64: one wavefront per group, whose best paths a second
+   kernel reduces; else the whole vector), work items (vector, path group)
+   per workgroup, 1 if the items are numbered path group major (all
+   vectors' first group, then the second, ...) else 0, workgroups}.  Errors: MPNL_E_INVAL for a null batch or a
    negative max. */
 int mpnl_batch_info(const mpnl_batch *batch, int *n_launches, int *shapes,
                     int max);
@@ -319,12 +345,16 @@ int mpnl_batch_info(const mpnl_batch *batch, int *n_launches, int *shapes,
 int mpnl_batch_destroy(mpnl_ctx *ctx, mpnl_batch *batch);
 
 /* ---- serving: continuous batching of arriving slot jobs -------------------- */
-/* The detector run as a service (motivated by the centralised DU serving
-   many radio units in the paper's introduction): slot-detection jobs arrive
-   over time, wait for admission, are merged into launches and complete
-   asynchronously.  The scheduler is host code behind an executor interface;
-   the device executor runs each launch as one mpnl_detect_batch() on its own
-   stream, so launches overlap on the GPU, and times completion with events. */
+/* The detector run as a service for the pooled processing of Sec. II-A (a
+   distributed unit serving the slots of many radio units as their traffic
+   arrives): slot-detection jobs arrive over time, wait for admission, are
+   merged into launches and complete asynchronously.  A job larger than
+   split_vectors runs as pieces of whole subcarriers (subcarriers are
+   independent, so its result does not change), which lets smaller jobs run
+   between the pieces of a large one.  The scheduler is host code behind an
+   executor interface; the device executor runs each launch as one
+   mpnl_detect_batch() on its own stream, so launches overlap on the GPU,
+   and times completion with events. */
 
 typedef struct mpnl_server mpnl_server;
 
@@ -337,8 +367,26 @@ typedef struct {
                             it is rejected (0: no limit)                    */
     double deadline_us;  /* latency target (arrival to completion)          */
     int drop_late;       /* 1: a job that has already waited past the
-                            deadline when it would be admitted is dropped   */
+                            deadline when it would be admitted (and none of
+                            whose pieces has started) is dropped             */
+    int policy;          /* admission order: MPNL_SCHED_FIFO or
+                            MPNL_SCHED_SLACK                                */
+    int64_t split_vectors; /* a job with more received vectors (S * T) runs
+                            as pieces of whole subcarriers, each of at most
+                            max(T, split_vectors) vectors (0: never split)  */
+    double est_fixed_us; /* service-time model of the slack policy: a piece */
+    double est_us_per_gflop; /* takes est_fixed_us + est_us_per_gflop * its
+                            path-search GFLOP (4 N (N - 1) + 11 N flops per
+                            path and received vector)                       */
 } mpnl_server_config;
+
+/* admission orders */
+#define MPNL_SCHED_FIFO 0   /* arrival order; the head of the queue blocks   */
+#define MPNL_SCHED_SLACK 1  /* least slack first among the jobs that can
+   still meet the deadline, slack = arrival + deadline - now - estimated time
+   of the job's pieces not yet admitted; jobs that can no longer meet it
+   follow in arrival order.  The first piece in this order that does not fit
+   the budget waits for memory and blocks the rest.                        */
 
 /* job outcomes */
 #define MPNL_JOB_DONE 0
@@ -394,7 +442,9 @@ int mpnl_server_destroy(mpnl_server *srv);
 /* The same scheduler on a virtual clock with a modelled device, for tests of
    the serving logic without a GPU.  A launch takes launch_us +
    per_vector_us * (its S * T sum) (+ slow_extra_us if it holds job
-   slow_job) and launches run one after another; launch number fail_launch
+   slow_job) and launches run one after another.  A job split by
+   split_vectors becomes ceil(vectors / split_vectors) pieces of near-equal
+   vectors, with bytes and gflop shared in proportion; launch number fail_launch
    (0-based, -1 for none) fails with MPNL_E_HIP.  jobs must be sorted by
    arrival; out[i] receives job i's completion; n_launches (may be NULL)
    receives the number of launches. */
@@ -403,6 +453,7 @@ typedef struct {
     double arrival_us;
     size_t bytes;
     int64_t vectors;
+    double gflop;        /* path-search work (slack policy's estimate)     */
 } mpnl_sim_job;
 
 typedef struct {

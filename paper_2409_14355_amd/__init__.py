@@ -50,7 +50,9 @@ STAGE_NAMES = ("sqrd", "posvec", "rotate", "paths", "bound")
 class mpnl_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_batch_jobs", ctypes.c_int),
                 ("max_inflight", ctypes.c_int), ("max_queue", ctypes.c_int),
-                ("deadline_us", ctypes.c_double), ("drop_late", ctypes.c_int)]
+                ("deadline_us", ctypes.c_double), ("drop_late", ctypes.c_int), ("policy", ctypes.c_int),
+                ("split_vectors", ctypes.c_int64), ("est_fixed_us", ctypes.c_double),
+                ("est_us_per_gflop", ctypes.c_double)]
 
 
 class mpnl_completion(ctypes.Structure):
@@ -61,7 +63,7 @@ class mpnl_completion(ctypes.Structure):
 
 class mpnl_sim_job(ctypes.Structure):
     _fields_ = [("id", ctypes.c_int64), ("arrival_us", ctypes.c_double), ("bytes", ctypes.c_size_t),
-                ("vectors", ctypes.c_int64)]
+                ("vectors", ctypes.c_int64), ("gflop", ctypes.c_double)]
 
 
 class mpnl_sim_device(ctypes.Structure):
@@ -285,10 +287,10 @@ def mpnl_batch_run(ctx: int, batch: int, jobs: Sequence[dict], stream=None) -> N
 def mpnl_batch_info(batch: int, max_launches: int = 128) -> list[dict]:
     """-> launch shape of every path-search launch of the plan."""
     n = ctypes.c_int()
-    v = (ctypes.c_int * (5 * max_launches))()
+    v = (ctypes.c_int * (7 * max_launches))()
     _check(lib().mpnl_batch_info(batch, ctypes.byref(n), v, max_launches), "mpnl_batch_info")
-    keys = ("N", "mod", "lanes", "vectors_per_workgroup", "workgroups")
-    return [dict(zip(keys, v[5 * i:5 * i + 5])) for i in range(min(n.value, max_launches))]
+    keys = ("N", "mod", "lanes", "group_lanes", "items_per_workgroup", "group_major", "workgroups")
+    return [dict(zip(keys, v[7 * i:7 * i + 7])) for i in range(min(n.value, max_launches))]
 
 
 def mpnl_batch_destroy(ctx: int, batch: int) -> None:
@@ -481,10 +483,15 @@ class BatchPlan:
         self.handle = 0
 
 
+MPNL_SCHED_FIFO, MPNL_SCHED_SLACK = 0, 1
+
+
 def server_config(hbm_budget: int = 0, max_batch_jobs: int = 8, max_inflight: int = 2,
-                  max_queue: int = 0, deadline_us: float = 500.0, drop_late: bool = False):
+                  max_queue: int = 0, deadline_us: float = 500.0, drop_late: bool = False,
+                  policy: int = MPNL_SCHED_FIFO, split_vectors: int = 0, est_fixed_us: float = 40.0,
+                  est_us_per_gflop: float = 20.0):
     return mpnl_server_config(hbm_budget, max_batch_jobs, max_inflight, max_queue, deadline_us,
-                              1 if drop_late else 0)
+                              1 if drop_late else 0, policy, split_vectors, est_fixed_us, est_us_per_gflop)
 
 
 def _completions(arr) -> list[dict]:
@@ -500,11 +507,11 @@ def mpnl_sched_simulate(cfg: mpnl_server_config, jobs: Sequence[dict], launch_us
                         per_vector_us: float = 0.0, fail_launch: int = -1, slow_job: int = -1,
                         slow_extra_us: float = 0.0):
     """Scheduler on a virtual clock with a modelled device.  jobs: dicts
-    {arrival_us, bytes, vectors} in arrival order (ids are their positions).
-    -> (completions by id, number of launches)."""
+    {arrival_us, bytes, vectors, gflop} in arrival order (ids are their
+    positions).  -> (completions by id, number of launches)."""
     arr = (mpnl_sim_job * len(jobs))()
     for i, j in enumerate(jobs):
-        arr[i] = mpnl_sim_job(i, j["arrival_us"], j.get("bytes", 0), j.get("vectors", 0))
+        arr[i] = mpnl_sim_job(i, j["arrival_us"], j.get("bytes", 0), j.get("vectors", 0), j.get("gflop", 0.0))
     dev = mpnl_sim_device(launch_us, per_vector_us, fail_launch, slow_job, slow_extra_us)
     out = (mpnl_completion * max(len(jobs), 1))()
     n = ctypes.c_int()

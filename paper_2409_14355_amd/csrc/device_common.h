@@ -403,6 +403,8 @@ struct PathArgs {
     float *part;           // per path group best (metric, path, decisions) or null
     float *bound;          // (T, S) metric of path 0 per vector (pruning), or null
     int S, T, N, K, NP;
+    int ipw;               // path_search_kernel: work items (vector, path group) per workgroup
+    int gmajor;            // path_search_kernel: 1 = work items numbered path group major
     float sigma2, clip;
 };
 
@@ -698,28 +700,76 @@ struct MultiOccupancy {
     static constexpr int waves = PREC == PREC_FP32 ? 8 : 6;
 };
 
-// grid: (S * T) x path groups; partials: (S * T, groups, 2 + (N + 3) / 4)
+// Work item (vector, path group) of slot q of workgroup b, for nvec vectors
+// of `groups` path groups, ipw items a workgroup.  Vector-major: the groups
+// of a vector are neighbours.  Group-major: all vectors' group 0 first, then
+// group 1, ... (a workgroup holds ipw vectors of one group), which is the
+// order in which the groups' costs are most alike when a launch fills the
+// device.  Either way every XCD gets a contiguous range of vectors, so the
+// blocks of one subcarrier share an L2.
+__device__ __forceinline__ void work_item(int b, int nblocks, int q, int nvec, int groups, int ipw, bool gmajor,
+                                          int &vi, int &g)
+{
+    if (gmajor) {
+        const int nvb = (nvec + ipw - 1) / ipw;  // workgroups per group
+        g = b / nvb;
+        vi = xcd_remap(b - g * nvb, nvb) * ipw + q;
+    } else {
+        const int w = xcd_remap(b, nblocks) * ipw + q;
+        vi = w / groups;
+        g = w - vi * groups;
+    }
+}
+
+// Work items (received vector, path group of one wavefront), ipw of them per
+// workgroup (block = 64 ipw lanes, no barrier between the wavefronts);
+// vectors numbered subcarrier-major (s T + t).
+// partials: (S * T, groups, 2 + (N + 3) / 4)
 template <int N, int L, int PREC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void path_search_kernel(PathArgs a)
 {
     __shared__ float sm[4];
     __shared__ int sr[4];
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int groups = (a.K + 63) / 64;
+    const int q = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    int vi, g;
+    work_item(blockIdx.x, gridDim.x, q, a.S * a.T, groups, a.ipw, a.gmajor != 0, vi, g);
+    const bool active = vi < a.S * a.T && g < groups;
+    const int lb = active ? vi : a.S * a.T - 1;
     const int s = lb / a.T, t = lb - s * a.T;
     const size_t sN = (size_t)s * N;
     const size_t v = (size_t)t * a.S + s;
     cptr<uint32_t> rq = a.rq ? uniform_ptr(a.rq + sN * N) : nullptr;
-    float *part = a.part ? a.part + (v * gridDim.y + blockIdx.y) * (2 + (N + 3) / 4) : nullptr;
+    float *part = a.part ? a.part + (v * groups + g) * (2 + (N + 3) / 4) : nullptr;
     const float b0 = a.bound ? uniform_ptr(a.bound + v)[0] : INFINITY;
     const float *b0d = a.bound ? a.bound + (size_t)a.S * a.T + v * ((N + 3) / 4) : nullptr;
     search_vector<N, L, PREC>(uniform_ptr(a.yt + v * N), uniform_ptr(a.diag + sN), uniform_ptr(a.rlat + sN * N),
                               rq, a.P + (size_t)s * a.K * a.NP, a.order ? a.order + (size_t)s * a.K : nullptr,
-                              a.K, a.NP, blockIdx.y, a.permd + sN, a.out + v * N, part, sm, sr, (int)blockDim.x,
-                              (int)threadIdx.x, true, b0, b0d);
+                              a.K, a.NP, g, a.permd + sN, a.out + v * N, part, sm, sr, 64,
+                              (int)(threadIdx.x & 63u), active, b0, b0d);
 }
 
-// Best of the path groups of every received vector (equal metrics: lowest
-// path), written in user order.  One lane per vector.
+// Best of the path groups of one received vector (equal metrics: lowest
+// path), written in user order.  p: the vector's `groups` partial records of
+// 2 + (N + 3) / 4 floats (metric, path, packed decisions).
+template <int L>
+__device__ __forceinline__ void reduce_groups(const float *p, int groups, int N, const int32_t *pm, int32_t *o)
+{
+    const int stride = 2 + (N + 3) / 4;
+    int best = 0;
+    for (int g = 1; g < groups; ++g)
+        if (better(p[g * stride], __float_as_int(p[g * stride + 1]), p[best * stride],
+                   __float_as_int(p[best * stride + 1])))
+            best = g;
+    const float *dec = p + best * stride + 2;
+    for (int d = 0; d < N; ++d) {
+        const int u = pm[d];
+        if ((unsigned)u < (unsigned)N)
+            o[u] = decision_index<L>(dec, d);
+    }
+}
+
+// One lane per received vector.
 template <int L>
 __global__ __launch_bounds__(256) void path_group_reduce_kernel(PathArgs a, int groups)
 {
@@ -727,21 +777,8 @@ __global__ __launch_bounds__(256) void path_group_reduce_kernel(PathArgs a, int 
     if (v >= (size_t)a.S * a.T)
         return;
     const int N = a.N;
-    const int stride = 2 + (N + 3) / 4;
-    const float *p = a.part + v * groups * stride;
-    int best = 0;
-    for (int g = 1; g < groups; ++g)
-        if (better(p[g * stride], __float_as_int(p[g * stride + 1]), p[best * stride],
-                   __float_as_int(p[best * stride + 1])))
-            best = g;
-    const float *dec = p + best * stride + 2;
     const int s = (int)(v % a.S);
-    const int32_t *pm = a.permd + (size_t)s * N;
-    for (int d = 0; d < N; ++d) {
-        const int u = pm[d];
-        if ((unsigned)u < (unsigned)N)
-            a.out[v * N + u] = decision_index<L>(dec, d);
-    }
+    reduce_groups<L>(a.part + v * groups * (2 + (N + 3) / 4), groups, N, a.permd + (size_t)s * N, a.out + v * N);
 }
 
 // ============================================================================
@@ -852,16 +889,28 @@ __global__ __launch_bounds__(256) void path_search_soft_kernel(PathArgs a)
 }
 
 // ============================================================================
-// Path search over many jobs (cells) that share the user count N and the
-// modulation.  Work items are (job, subcarrier, symbol), numbered job by job.
-// A workgroup holds vpw received vectors of W = blockDim / vpw lanes each:
-// vector slot q of workgroup b runs item b * vpw + q exactly as
-// path_search_kernel runs it, so a job's result does not depend on the other
-// jobs of the launch or on vpw.
+// Path search over many jobs (cells) that share the user count N, the
+// modulation and the lanes per received vector (paths rounded up to a
+// wavefront).  Received vectors are numbered job by job, (job, subcarrier,
+// symbol), subcarrier-major.  Each vector's paths split into `groups` path
+// groups of gw = lanes / groups lanes (whole wavefronts); a workgroup runs
+// ipw work items (vector, group).
+// Item (vector, g) (numbered as work_item says) runs paths g gw .. g gw +
+// gw - 1 exactly as path_search_kernel runs them, so a job's result depends neither on the
+// other jobs of the launch nor on the launch shape.  With one group the
+// winner writes the vector's symbols; with several, each group leaves its
+// best in the job's partial records (JobDev::part) for
+// path_group_reduce_multi_kernel.  One-wavefront groups (gw = 64) share no
+// barrier, so a wavefront that pruning stops early frees its slot at once.
 // ============================================================================
 struct MultiArgs {
     const JobDev *jobs;
-    int n_jobs, total_items, vpw;
+    int n_jobs;
+    int total_items;  // received vectors of all jobs
+    int ipw;          // work items per workgroup
+    int gw;           // lanes per path group (64 or the whole vector's lanes)
+    int groups;       // path groups per vector
+    int gmajor;       // 1: work items numbered path group major (work_item)
 };
 
 template <int N, int L, int PREC>
@@ -870,22 +919,43 @@ path_search_multi_kernel(MultiArgs a)
 {
     __shared__ float sm[4];
     __shared__ int sr[4];
-    const int W = (int)blockDim.x / a.vpw;
-    const int q = __builtin_amdgcn_readfirstlane((int)threadIdx.x / W);  // whole waves per slot
-    const int item = xcd_remap(blockIdx.x, gridDim.x) * a.vpw + q;
-    const bool active = item < a.total_items;
-    const JobDev &j = a.jobs[find_job(a.jobs, a.n_jobs, active ? item : a.total_items - 1)];
-    const int li = (active ? item : a.total_items - 1) - j.item_begin;
+    constexpr int NW = (N + 3) / 4;
+    const int W = a.gw;
+    const int q = __builtin_amdgcn_readfirstlane((int)threadIdx.x / W);  // whole waves per item
+    int vitem, g;
+    work_item(blockIdx.x, gridDim.x, q, a.total_items, a.groups, a.ipw, a.gmajor != 0, vitem, g);
+    const bool active = vitem < a.total_items && g < a.groups;
+    const int item = active ? vitem : a.total_items - 1;
+    const JobDev &j = a.jobs[find_job(a.jobs, a.n_jobs, item)];
+    const int li = item - j.item_begin;
     const int s = li / j.T, t = li - s * j.T;
     const size_t sN = (size_t)s * N;
     const size_t v = (size_t)t * j.S + s;
     cptr<uint32_t> rq = j.rq ? uniform_ptr(j.rq + sN * N) : nullptr;
     const float b0 = j.bound ? uniform_ptr(j.bound + v)[0] : INFINITY;
-    const float *b0d = j.bound ? j.bound + (size_t)j.S * j.T + v * ((N + 3) / 4) : nullptr;
+    const float *b0d = j.bound ? j.bound + (size_t)j.S * j.T + v * NW : nullptr;
+    float *part = a.groups > 1 ? j.part + (v * a.groups + g) * (2 + NW) : nullptr;
     search_vector<N, L, PREC>(uniform_ptr(j.yt + v * N), uniform_ptr(j.diag + sN), uniform_ptr(j.rlat + sN * N), rq,
                               j.P + (size_t)s * j.K * j.NP, j.order ? j.order + (size_t)s * j.K : nullptr, j.K,
-                              j.NP, 0, j.permd + sN, j.out + v * N, nullptr, sm, sr, W, (int)threadIdx.x - q * W,
+                              j.NP, g, j.permd + sN, j.out + v * N, part, sm, sr, W, (int)threadIdx.x - q * W,
                               active, b0, b0d);
+}
+
+// Best of the path groups of every received vector of a multi-job launch.
+// One lane per received vector (numbered as in path_search_multi_kernel).
+template <int L>
+__global__ __launch_bounds__(64) void path_group_reduce_multi_kernel(MultiArgs a)
+{
+    const int item = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (item >= a.total_items)
+        return;
+    const JobDev &j = a.jobs[find_job(a.jobs, a.n_jobs, item)];
+    const int li = item - j.item_begin;
+    const int s = li / j.T, t = li - s * j.T;
+    const size_t v = (size_t)t * j.S + s;
+    const int N = j.N;
+    reduce_groups<L>(j.part + v * a.groups * (2 + (N + 3) / 4), a.groups, N, j.permd + (size_t)s * N,
+                     j.out + v * N);
 }
 
 // ============================================================================

@@ -3,286 +3,46 @@
 
 namespace mpnl {
 
-hipError_t path_launch_n1(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n2(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n3(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n4(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n5(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n6(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n7(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n8(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n9(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n10(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n11(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n12(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n13(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n14(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n15(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n16(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n17(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n18(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n19(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n20(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n21(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n22(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n23(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n24(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n25(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n26(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n27(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n28(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n29(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n30(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n31(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_launch_n32(const dev::PathArgs &, int, int, hipStream_t);
+// One launcher per user count 1..32 of each kind (defined in path_n<N>.hip and
+// path_bucket<NMAX>.hip); the tables below are indexed by N - 1.
+#define MPNL_FOR_N(X)                                                                                   \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) \
+        X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+
+#define MPNL_DECLARE(n)                                                                 \
+    hipError_t path_launch_n##n(const dev::PathArgs &, int, int, hipStream_t);          \
+    hipError_t path_multi_launch_n##n(const dev::MultiArgs &, int, int, int, int, hipStream_t); \
+    hipError_t path_bound_launch_n##n(const dev::PathArgs &, int, int, hipStream_t);    \
+    hipError_t path_bound_multi_launch_n##n(const JobDev *, int, int, int, int, hipStream_t);
+MPNL_FOR_N(MPNL_DECLARE)
+#undef MPNL_DECLARE
 hipError_t soft_launch_nmax8(const dev::PathArgs &, int, hipStream_t);
 hipError_t soft_launch_nmax16(const dev::PathArgs &, int, hipStream_t);
 hipError_t soft_launch_nmax24(const dev::PathArgs &, int, hipStream_t);
 hipError_t soft_launch_nmax32(const dev::PathArgs &, int, hipStream_t);
 
-hipError_t path_multi_launch_n1(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n2(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n3(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n4(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n5(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n6(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n7(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n8(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n9(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n10(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n11(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n12(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n13(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n14(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n15(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n16(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n17(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n18(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n19(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n20(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n21(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n22(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n23(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n24(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n25(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n26(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n27(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n28(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n29(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n30(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n31(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-hipError_t path_multi_launch_n32(const dev::MultiArgs &, int, int, int, int, hipStream_t);
-
-hipError_t path_bound_launch_n1(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n2(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n3(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n4(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n5(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n6(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n7(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n8(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n9(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n10(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n11(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n12(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n13(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n14(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n15(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n16(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n17(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n18(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n19(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n20(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n21(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n22(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n23(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n24(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n25(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n26(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n27(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n28(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n29(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n30(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n31(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_launch_n32(const dev::PathArgs &, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n1(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n2(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n3(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n4(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n5(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n6(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n7(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n8(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n9(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n10(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n11(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n12(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n13(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n14(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n15(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n16(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n17(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n18(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n19(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n20(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n21(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n22(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n23(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n24(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n25(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n26(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n27(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n28(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n29(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n30(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n31(const JobDev *, int, int, int, int, hipStream_t);
-hipError_t path_bound_multi_launch_n32(const JobDev *, int, int, int, int, hipStream_t);
-
 namespace {
+
 using namespace dev;
 
 typedef hipError_t (*PathLaunch)(const PathArgs &, int, int, hipStream_t);
-const PathLaunch kPathLaunch[32] = {
-    path_launch_n1,
-    path_launch_n2,
-    path_launch_n3,
-    path_launch_n4,
-    path_launch_n5,
-    path_launch_n6,
-    path_launch_n7,
-    path_launch_n8,
-    path_launch_n9,
-    path_launch_n10,
-    path_launch_n11,
-    path_launch_n12,
-    path_launch_n13,
-    path_launch_n14,
-    path_launch_n15,
-    path_launch_n16,
-    path_launch_n17,
-    path_launch_n18,
-    path_launch_n19,
-    path_launch_n20,
-    path_launch_n21,
-    path_launch_n22,
-    path_launch_n23,
-    path_launch_n24,
-    path_launch_n25,
-    path_launch_n26,
-    path_launch_n27,
-    path_launch_n28,
-    path_launch_n29,
-    path_launch_n30,
-    path_launch_n31,
-    path_launch_n32};
-
 typedef hipError_t (*MultiLaunch)(const MultiArgs &, int, int, int, int, hipStream_t);
-const MultiLaunch kMultiLaunch[32] = {
-    path_multi_launch_n1,
-    path_multi_launch_n2,
-    path_multi_launch_n3,
-    path_multi_launch_n4,
-    path_multi_launch_n5,
-    path_multi_launch_n6,
-    path_multi_launch_n7,
-    path_multi_launch_n8,
-    path_multi_launch_n9,
-    path_multi_launch_n10,
-    path_multi_launch_n11,
-    path_multi_launch_n12,
-    path_multi_launch_n13,
-    path_multi_launch_n14,
-    path_multi_launch_n15,
-    path_multi_launch_n16,
-    path_multi_launch_n17,
-    path_multi_launch_n18,
-    path_multi_launch_n19,
-    path_multi_launch_n20,
-    path_multi_launch_n21,
-    path_multi_launch_n22,
-    path_multi_launch_n23,
-    path_multi_launch_n24,
-    path_multi_launch_n25,
-    path_multi_launch_n26,
-    path_multi_launch_n27,
-    path_multi_launch_n28,
-    path_multi_launch_n29,
-    path_multi_launch_n30,
-    path_multi_launch_n31,
-    path_multi_launch_n32,
-};
-
 typedef hipError_t (*BoundLaunch)(const PathArgs &, int, int, hipStream_t);
-const BoundLaunch kBoundLaunch[32] = {
-    path_bound_launch_n1,
-    path_bound_launch_n2,
-    path_bound_launch_n3,
-    path_bound_launch_n4,
-    path_bound_launch_n5,
-    path_bound_launch_n6,
-    path_bound_launch_n7,
-    path_bound_launch_n8,
-    path_bound_launch_n9,
-    path_bound_launch_n10,
-    path_bound_launch_n11,
-    path_bound_launch_n12,
-    path_bound_launch_n13,
-    path_bound_launch_n14,
-    path_bound_launch_n15,
-    path_bound_launch_n16,
-    path_bound_launch_n17,
-    path_bound_launch_n18,
-    path_bound_launch_n19,
-    path_bound_launch_n20,
-    path_bound_launch_n21,
-    path_bound_launch_n22,
-    path_bound_launch_n23,
-    path_bound_launch_n24,
-    path_bound_launch_n25,
-    path_bound_launch_n26,
-    path_bound_launch_n27,
-    path_bound_launch_n28,
-    path_bound_launch_n29,
-    path_bound_launch_n30,
-    path_bound_launch_n31,
-    path_bound_launch_n32,
-};
-
 typedef hipError_t (*BoundMultiLaunch)(const JobDev *, int, int, int, int, hipStream_t);
-const BoundMultiLaunch kBoundMultiLaunch[32] = {
-    path_bound_multi_launch_n1,
-    path_bound_multi_launch_n2,
-    path_bound_multi_launch_n3,
-    path_bound_multi_launch_n4,
-    path_bound_multi_launch_n5,
-    path_bound_multi_launch_n6,
-    path_bound_multi_launch_n7,
-    path_bound_multi_launch_n8,
-    path_bound_multi_launch_n9,
-    path_bound_multi_launch_n10,
-    path_bound_multi_launch_n11,
-    path_bound_multi_launch_n12,
-    path_bound_multi_launch_n13,
-    path_bound_multi_launch_n14,
-    path_bound_multi_launch_n15,
-    path_bound_multi_launch_n16,
-    path_bound_multi_launch_n17,
-    path_bound_multi_launch_n18,
-    path_bound_multi_launch_n19,
-    path_bound_multi_launch_n20,
-    path_bound_multi_launch_n21,
-    path_bound_multi_launch_n22,
-    path_bound_multi_launch_n23,
-    path_bound_multi_launch_n24,
-    path_bound_multi_launch_n25,
-    path_bound_multi_launch_n26,
-    path_bound_multi_launch_n27,
-    path_bound_multi_launch_n28,
-    path_bound_multi_launch_n29,
-    path_bound_multi_launch_n30,
-    path_bound_multi_launch_n31,
-    path_bound_multi_launch_n32,
-};
+
+#define MPNL_ENTRY(n) path_launch_n##n,
+const PathLaunch kPathLaunch[32] = {MPNL_FOR_N(MPNL_ENTRY)};
+#undef MPNL_ENTRY
+#define MPNL_ENTRY(n) path_multi_launch_n##n,
+const MultiLaunch kMultiLaunch[32] = {MPNL_FOR_N(MPNL_ENTRY)};
+#undef MPNL_ENTRY
+#define MPNL_ENTRY(n) path_bound_launch_n##n,
+const BoundLaunch kBoundLaunch[32] = {MPNL_FOR_N(MPNL_ENTRY)};
+#undef MPNL_ENTRY
+#define MPNL_ENTRY(n) path_bound_multi_launch_n##n,
+const BoundMultiLaunch kBoundMultiLaunch[32] = {MPNL_FOR_N(MPNL_ENTRY)};
+#undef MPNL_ENTRY
+#undef MPNL_FOR_N
 
 PathArgs path_args(const SlotDev &sd, const float2 *yt, int T, int32_t *out)
 {
@@ -303,6 +63,8 @@ PathArgs path_args(const SlotDev &sd, const float2 *yt, int T, int32_t *out)
     a.N = sd.N;
     a.K = sd.K;
     a.NP = sd.NP;
+    a.ipw = 1;
+    a.gmajor = 1;
     a.sigma2 = 1.f;
     a.clip = 0.f;
     return a;
@@ -337,6 +99,14 @@ hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_
             return hipErrorInvalidValue;
         a.part = part;
     }
+    if ((long long)sd.S * T * groups > INT_MAX)
+        return hipErrorInvalidValue;
+    // one-wavefront path groups, one a workgroup, group major (measured on
+    // MI355X, 16 users x 1200 x 14, 256 paths: 0.092 ms against 0.150 ms
+    // vector major; vector major needs four items a workgroup to reach
+    // 0.095 ms; 24 users x 3276 x 14: 0.253 against 0.270 at best)
+    a.ipw = 1;
+    a.gmajor = 1;
     hipError_t e = kPathLaunch[sd.N - 1](a, sd.bits, precision, st);
     if (e != hipSuccess || groups <= 1)
         return e;
@@ -386,18 +156,35 @@ hipError_t launch_path_bound_multi(const JobDev *jobs_dev, int n_jobs, int bound
 }
 
 hipError_t launch_path_search_multi(const JobDev *jobs_dev, int n_jobs, int total_items, int N, int bits,
-                                    int precision, int threads, int vpw, hipStream_t st)
+                                    int precision, int threads, int groups, int ipw, int gmajor, hipStream_t st)
 {
-    if (N < 1 || N > 32 || threads < 64 || threads % 64 || (vpw != 1 && vpw != 2 && vpw != 4) ||
-        threads * vpw > 256 || total_items < 1)
+    if (N < 1 || N > 32 || threads < 64 || threads > 256 || threads % 64 || groups < 1 || threads % groups ||
+        (threads / groups) % 64 || (ipw != 1 && ipw != 2 && ipw != 4) || ipw * (threads / groups) > 256 ||
+        total_items < 1)
         return hipErrorInvalidValue;
     MultiArgs a;
     a.jobs = jobs_dev;
     a.n_jobs = n_jobs;
     a.total_items = total_items;
-    a.vpw = vpw;
-    const int grid = (total_items + vpw - 1) / vpw;
-    return kMultiLaunch[N - 1](a, bits, precision, threads * vpw, grid, st);
+    a.ipw = ipw;
+    a.gw = threads / groups;
+    a.groups = groups;
+    a.gmajor = gmajor;
+    const long long nvb = ((long long)total_items + ipw - 1) / ipw;  // workgroups per path group
+    if (nvb * groups > INT_MAX)
+        return hipErrorInvalidValue;
+    const int grid = (int)(nvb * groups);
+    hipError_t e = kMultiLaunch[N - 1](a, bits, precision, ipw * a.gw, grid, st);
+    if (e != hipSuccess || groups == 1)
+        return e;
+    const dim3 rgrid((total_items + 63) / 64), rblock(64);  // one lane a vector
+    if (bits == 2)
+        hipLaunchKernelGGL(path_group_reduce_multi_kernel<2>, rgrid, rblock, 0, st, a);
+    else if (bits == 4)
+        hipLaunchKernelGGL(path_group_reduce_multi_kernel<4>, rgrid, rblock, 0, st, a);
+    else
+        hipLaunchKernelGGL(path_group_reduce_multi_kernel<8>, rgrid, rblock, 0, st, a);
+    return hipGetLastError();
 }
 
 }  // namespace mpnl

@@ -39,6 +39,7 @@ struct JobDev {
     const uint16_t *order;
     int32_t *out;          // (T, S, N)
     float *bound;          // pruning record (bound_record_bytes), or null
+    float *part;           // per path group best of every vector (multi_partial_bytes), or null
     int S, T, N, K, NP;
     int item_begin;        // first global work item of this job
     int bound_begin;       // first item of this job in the bound launch (ceil(S T / 64) items a job)
@@ -51,13 +52,22 @@ inline size_t bound_record_bytes(int S, int T, int N)
     return (size_t)S * T * (1 + (N + 3) / 4) * sizeof(float);
 }
 
+// Partial records of a multi-job launch that splits each vector's K paths
+// into path groups of one wavefront: (T, S, groups) records of 2 + (N + 3) / 4
+// floats (metric, path, packed decisions); 0 with a single group.
+inline size_t multi_partial_bytes(int S, int T, int N, int K)
+{
+    const int groups = (K + 63) / 64;
+    return groups > 1 ? (size_t)S * T * groups * (2 + (N + 3) / 4) * sizeof(float) : 0;
+}
+
 // Kernel launchers (enqueue only; return hipError_t of the launch).
 // a1; writes R both as is (roff) and in lattice units (rlat, rlat_h, rlat_b).
 hipError_t launch_sqrd(const float2 *H, const SlotDev &sd, hipStream_t st);
 hipError_t launch_posvec(const SlotDev &sd, hipStream_t st);
 hipError_t launch_rotate(const SlotDev &sd, const float2 *y, int T, float2 *yt, hipStream_t st);
-// K > 256 paths run as ceil(K / 256) workgroups per vector whose best
-// paths meet in `part` (path_partial_bytes(); null when K <= 256).
+// K > 64 paths run as ceil(K / 64) one-wavefront workgroups per vector whose
+// best paths meet in `part` (path_partial_bytes(); null when K <= 64).
 size_t path_partial_bytes(const SlotDev &sd, int T);
 hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_t *out,
                               int precision, float *part, float *bound, hipStream_t st);
@@ -68,7 +78,7 @@ hipError_t launch_path_bound(const SlotDev &sd, const float2 *yt, int T, int pre
                              hipStream_t st);
 hipError_t launch_path_search_soft(const SlotDev &sd, const float2 *yt, int T, float sigma2,
                                    float clip, float *llr, int32_t *out, hipStream_t st);
-// Batched path search over many jobs sharing (NMAX bucket, bits); one persistent launch.
+// Regularised (MMSE-extended) system of the overloaded detection:
 // H_x = [H; sigma I] ((S, M + N, N)) and y_x = [y; 0] ((T, S, M + N)).
 hipError_t launch_extend(const float2 *H, const float2 *y, int S, int T, int M, int N, float sigma, float2 *Hx,
                          float2 *yx, hipStream_t st);
@@ -77,12 +87,17 @@ hipError_t launch_extend(const float2 *H, const float2 *y, int S, int T, int M, 
 hipError_t launch_mmse(const float2 *H, const float2 *y, int S, int T, int M, int N, int bits, float sigma2,
                        int32_t *out, hipStream_t st);
 
-// Path search of many jobs with the same N and modulation (each with
-// n_paths <= threads, threads a multiple of 64), one work item (job,
-// subcarrier, symbol) per `threads` lanes, vpw in {1, 2, 4} items per
-// workgroup (threads * vpw <= 256).
+// Path search of many jobs with the same N, modulation and lanes per
+// received vector (`threads`: n_paths rounded up to a multiple of 64, at most
+// 256).  Each vector's paths run as `groups` path groups of threads / groups
+// lanes (groups = 1, or threads / 64 for one-wavefront groups), `ipw` work
+// items (vector, group) per workgroup (ipw * threads / groups <= 256),
+// numbered path group major (gmajor = 1) or vector major.  With several
+// groups every job needs JobDev::part, and a second small kernel takes the
+// best group of every vector.
 hipError_t launch_path_search_multi(const JobDev *jobs_dev, int n_jobs, int total_items, int N, int bits,
-                                    int precision, int threads, int vpw, hipStream_t st);
+                                    int precision, int threads, int groups, int ipw, int gmajor,
+                                    hipStream_t st);
 // Pruning records (path 0 of every vector) for the jobs of a multi-job
 // launch whose JobDev::bound is set: ceil(S T / 64) items per job, numbered
 // from JobDev::bound_begin.  Run before launch_path_search_multi.

@@ -1,3 +1,3 @@
-// Soft-output and batched path-search kernels for 17..24 users.
+// Soft-output path-search kernels for 17..24 users.
 #define MPNL_NMAX 24
 #include "path_bucket.inc"

@@ -1,3 +1,3 @@
-// Soft-output and batched path-search kernels for 25..32 users.
+// Soft-output path-search kernels for 25..32 users.
 #define MPNL_NMAX 32
 #include "path_bucket.inc"

@@ -1,3 +1,3 @@
-// Soft-output and batched path-search kernels for 1..8 users.
+// Soft-output path-search kernels for 1..8 users.
 #define MPNL_NMAX 8
 #include "path_bucket.inc"

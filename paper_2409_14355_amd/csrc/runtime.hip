@@ -932,7 +932,8 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
         }
         batched[i] = 1;
         rc = pool_alloc(ctx, align_up((size_t)j.T * j.S * j.N * sizeof(float2)) +
-                                 (ctx->prune ? mpnl::bound_record_bytes(j.S, j.T, j.N) : 0),
+                                 (ctx->prune ? align_up(mpnl::bound_record_bytes(j.S, j.T, j.N)) : 0) +
+                                 mpnl::multi_partial_bytes(j.S, j.T, j.N, slots[i]->sd.K),
                         st, &ytb[i]);
         if (rc != MPNL_OK)
             break;
@@ -1018,10 +1019,14 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
                     const int i = groups[q].idx[u];
                     const mpnl::SlotDev &sd = slots[i]->sd;
                     mpnl::JobDev &J = jd[u];
-                    J.yt = (const float2 *)ctx->blocks[ytb[i]].ptr;
-                    J.bound = ctx->prune ? (float *)((char *)ctx->blocks[ytb[i]].ptr +
-                                                     align_up((size_t)jobs[i].T * sd.S * sd.N * sizeof(float2)))
-                                         : nullptr;
+                    char *wb = (char *)ctx->blocks[ytb[i]].ptr;
+                    const size_t yt_bytes = align_up((size_t)jobs[i].T * sd.S * sd.N * sizeof(float2));
+                    const size_t bd_bytes =
+                        ctx->prune ? align_up(mpnl::bound_record_bytes(sd.S, jobs[i].T, sd.N)) : 0;
+                    J.yt = (const float2 *)wb;
+                    J.bound = ctx->prune ? (float *)(wb + yt_bytes) : nullptr;
+                    J.part = mpnl::multi_partial_bytes(sd.S, jobs[i].T, sd.N, sd.K) ? (float *)(wb + yt_bytes + bd_bytes)
+                                                                                     : nullptr;
                     J.bound_begin = bacc;
                     bacc += (sd.S * jobs[i].T + 63) / 64;
                     J.rlat = sd.rlat;
@@ -1055,9 +1060,10 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
                                                       groups[q].bits, ctx->precision, st);
                 }
                 StageTimer tm(ctx, MPNL_STAGE_PATHS, st);
-                if (e == hipSuccess)
+                if (e == hipSuccess)  // one-wavefront path groups, group major, four per workgroup
                     e = mpnl::launch_path_search_multi(jd, (int)groups[q].idx.size(), items[q], groups[q].N,
-                                                   groups[q].bits, ctx->precision, threads[q], 1, st);
+                                                       groups[q].bits, ctx->precision, threads[q],
+                                                       threads[q] / 64, 4, 1, st);
             }
             if (e != hipSuccess)
                 rc = hip_fail(ctx, e);
@@ -1150,9 +1156,11 @@ struct PlanLaunch {
     int kind;
     int param;        // a1: MMAX; a2: E; a4: user count N
     int bits;         // a4
-    int threads;      // a4 workgroup size
+    int threads;      // a4: lanes per received vector (paths rounded up to 64)
     int nmax;         // a2: largest N (LDS size)
-    int vpw;          // a4: received vectors per workgroup (tuned)
+    int groups;       // a4: path groups per vector (threads / 64, or 1: the whole vector) (tuned)
+    int vpw;          // a4: work items (vector, path group) per workgroup (tuned)
+    int gmajor;       // a4: 1 = work items numbered path group major (tuned)
     int bound_items;  // a4: items of the pruning-bound launch
     int items;
     size_t off;       // byte offset of the job table in a table buffer
@@ -1168,6 +1176,7 @@ struct mpnl_batch {
     std::vector<mpnl::SlotDev> sd;
     std::vector<float2 *> yt;
     std::vector<float *> bound;  // per job pruning bounds, or null
+    std::vector<float *> part;   // per job path-group partial records, or null (one group)
     std::vector<PlanLaunch> launches;
     int block = -1;
     size_t table_bytes = 0;
@@ -1202,6 +1211,7 @@ void plan_fill(mpnl_batch *p, int b, const mpnl_job *jobs)
                 mpnl::JobDev &J = jd[u];
                 J.yt = p->yt[i];
                 J.bound = p->bound[i];
+                J.part = p->part[i];
                 J.bound_begin = bacc;
                 bacc += (sd.S * jobs[i].T + 63) / 64;
                 J.rlat = sd.rlat;
@@ -1269,15 +1279,18 @@ hipError_t plan_enqueue(mpnl_batch *p, int b, hipStream_t st, mpnl_ctx *timed = 
             }
             if (e == hipSuccess)
                 e = mpnl::launch_path_search_multi((const mpnl::JobDev *)tab, nj, L.items, L.param, L.bits,
-                                                   p->precision, L.threads, L.vpw, st);
+                                                   p->precision, L.threads, L.groups, L.vpw, L.gmajor, st);
         }
     }
     return e;
 }
 
-// Time every candidate shape (1, 2 or 4 received vectors per workgroup, as
-// the workgroup size allows) of every path-search launch on the first run's
-// data and keep the fastest (ties: fewer vectors per workgroup).
+// Time every candidate shape of every path-search launch on the first run's
+// data and keep the fastest: path groups of one wavefront or the whole
+// vector's lanes (one group), numbered group major or vector major, times 4,
+// 2 or 1 work items per workgroup as the workgroup size allows (ties: the
+// earlier candidate in that order).  Each candidate is timed with its group
+// reduction, the second of two passes.
 hipError_t plan_autotune(mpnl_batch *p, const mpnl_job *jobs, hipStream_t st)
 {
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -1286,7 +1299,7 @@ hipError_t plan_autotune(mpnl_batch *p, const mpnl_job *jobs, hipStream_t st)
         e = hipEventCreate(&t1);
     if (e == hipSuccess) {
         plan_fill(p, 0, jobs);
-        e = plan_enqueue(p, 0, st);  // produces yt, R and P of every job
+        e = plan_enqueue(p, 0, st);  // produces yt, R, P and the bounds of every job
     }
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
@@ -1296,26 +1309,34 @@ hipError_t plan_autotune(mpnl_batch *p, const mpnl_job *jobs, hipStream_t st)
         const mpnl::JobDev *tab = (const mpnl::JobDev *)(p->dev_table[0] + L.off);
         const int nj = (int)L.jobs.size();
         float best = 1e30f;
-        if (2 * L.threads > 256)
-            continue;  // a single candidate
-        for (int vpw = 1; vpw <= 4 && vpw * L.threads <= 256; vpw *= 2) {
-            float ms = 0.f;
-            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first pass warms up
-                e = hipEventRecord(t0, st);
-                if (e == hipSuccess)
-                    e = mpnl::launch_path_search_multi(tab, nj, L.items, L.param, L.bits, p->precision, L.threads,
-                                                       vpw, st);
-                if (e == hipSuccess)
-                    e = hipEventRecord(t1, st);
-                if (e == hipSuccess)
-                    e = hipEventSynchronize(t1);
-                if (e == hipSuccess)
-                    e = hipEventElapsedTime(&ms, t0, t1);
-            }
-            if (e == hipSuccess && ms < best) {
-                best = ms;
-                L.vpw = vpw;
-            }
+        const int group_choices[2] = {L.threads / 64, 1};
+        for (int gi = 0; gi < (L.threads > 64 ? 2 : 1); ++gi) {
+            const int groups = group_choices[gi];
+            const int gw = L.threads / groups;
+            for (int gmajor = 1; gmajor >= (groups > 1 ? 0 : 1); --gmajor)
+                for (int vpw = 4; vpw >= 1; vpw /= 2) {
+                    if (vpw * gw > 256)
+                        continue;
+                    float ms = 0.f;
+                    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first pass warms up
+                        e = hipEventRecord(t0, st);
+                        if (e == hipSuccess)
+                            e = mpnl::launch_path_search_multi(tab, nj, L.items, L.param, L.bits, p->precision,
+                                                               L.threads, groups, vpw, gmajor, st);
+                        if (e == hipSuccess)
+                            e = hipEventRecord(t1, st);
+                        if (e == hipSuccess)
+                            e = hipEventSynchronize(t1);
+                        if (e == hipSuccess)
+                            e = hipEventElapsedTime(&ms, t0, t1);
+                    }
+                    if (e == hipSuccess && ms < best) {
+                        best = ms;
+                        L.groups = groups;
+                        L.vpw = vpw;
+                        L.gmajor = gmajor;
+                    }
+                }
         }
     }
     if (t0)
@@ -1405,7 +1426,7 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
 
     // device memory: every job's slot state and rotated vectors
     std::vector<SlotLayout> lay(n_jobs);
-    std::vector<size_t> base(n_jobs), ytoff(n_jobs), boff(n_jobs);
+    std::vector<size_t> base(n_jobs), ytoff(n_jobs), boff(n_jobs), poff(n_jobs);
     size_t total = 0;
     for (int i = 0; i < n_jobs; ++i) {
         const mpnl_job &j = shapes[i];
@@ -1418,6 +1439,8 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
         boff[i] = total;
         if (ctx->prune)
             total += align_up(mpnl::bound_record_bytes(j.S, j.T, j.N));
+        poff[i] = total;
+        total += align_up(mpnl::multi_partial_bytes(j.S, j.T, j.N, K));
     }
     // launch groups
     auto group = [&](int kind, int param, int bits, int threads) -> PlanLaunch & {
@@ -1429,7 +1452,9 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
         L.param = param;
         L.bits = bits;
         L.threads = threads;
-        L.vpw = 1;
+        L.groups = kind == L_PATHS ? threads / 64 : 1;  // one-wavefront path groups, group major,
+        L.vpw = kind == L_PATHS ? 4 : 1;                 // four a workgroup, unless tuned
+        L.gmajor = 1;
         p->launches.push_back(L);
         return p->launches.back();
     };
@@ -1497,6 +1522,7 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
         p->sd.push_back(sd);
         p->yt.push_back((float2 *)(dbase + ytoff[i]));
         p->bound.push_back(ctx->prune ? (float *)(dbase + boff[i]) : nullptr);
+        p->part.push_back(mpnl::multi_partial_bytes(j.S, j.T, j.N, sd.K) ? (float *)(dbase + poff[i]) : nullptr);
     }
     hipError_t e = hipSuccess;
     for (int b = 0; b < kGraphCopies && e == hipSuccess; ++b) {
@@ -1566,12 +1592,14 @@ int mpnl_batch_info(const mpnl_batch *p, int *n_launches, int *shapes, int max)
     for (const PlanLaunch &L : p->launches)
         if (L.kind == L_PATHS) {
             if (shapes && n < max) {
-                int *o = shapes + 5 * n;
+                int *o = shapes + 7 * n;
                 o[0] = L.param;
                 o[1] = L.bits;
                 o[2] = L.threads;
-                o[3] = L.vpw;
-                o[4] = (L.items + L.vpw - 1) / L.vpw;
+                o[3] = L.threads / L.groups;
+                o[4] = L.vpw;
+                o[5] = L.gmajor;
+                o[6] = (int)(((long long)L.items + L.vpw - 1) / L.vpw * L.groups);
             }
             ++n;
         }

@@ -1,9 +1,10 @@
-// Serving core: slot-detection jobs arrive over time, wait in a FIFO for
-// admission (launch slots and the device-memory budget), are merged into
-// launches (continuous batching: whatever waits when a launch slot frees up
-// goes into the next launch) and complete asynchronously.  The scheduler
-// only talks to an Executor: the device executor runs a launch as one
-// mpnl_detect_batch() on its own stream and times it with events; the
+// Serving core: slot-detection jobs arrive over time, wait for admission
+// (launch slots and the device-memory budget), are merged into launches
+// (continuous batching: whatever waits when a launch slot frees up goes into
+// the next launch) and complete asynchronously.  A large job may run as
+// pieces of whole subcarriers; the job completes with its last piece.  The
+// scheduler only talks to an Executor: the device executor runs a launch as
+// one mpnl_detect_batch() on its own stream and times it with events; the
 // modelled executor runs on a virtual clock for tests without a GPU.
 #include "mpnl.h"
 
@@ -21,12 +22,18 @@
 namespace mpnl {
 namespace serve {
 
+// A unit of admission: a whole job, or one piece (a range of whole
+// subcarriers) of a split job.
 struct Job {
-    int64_t id;
+    int64_t id;        // the submitted job's id
     double arrival;
-    size_t bytes;
+    size_t bytes;      // device bytes while it runs
     int64_t vectors;
-    mpnl_job job;
+    double est_us;     // the slack policy's estimate of its service time
+    mpnl_job job;      // the piece's shape; H / y / out of the whole job
+    int s0 = 0;        // first subcarrier of the piece
+    int s_full = 0;    // subcarriers of the whole job (0: not split)
+    int parent = -1;   // scheduler's record of the submitted job
 };
 
 class Executor {
@@ -42,38 +49,66 @@ class Executor {
     virtual void release(int token) = 0;
 };
 
-mpnl_completion make_completion(const Job &j, int status, int error, double start, double done)
+mpnl_completion make_completion(int64_t id, double arrival, int status, int error, double start, double done)
 {
     mpnl_completion c;
-    c.id = j.id;
+    c.id = id;
     c.status = status;
     c.error = error;
-    c.arrival_us = j.arrival;
+    c.arrival_us = arrival;
     c.start_us = start;
     c.done_us = done;
     return c;
+}
+
+// Path-search GFLOP of a job shape: 4 N (N - 1) + 11 N flops per path and
+// received vector, paths clamped to |Q|^N.
+double job_gflop(const mpnl_job &j)
+{
+    double K = (double)j.n_paths;
+    const double q = (double)(1 << j.mod);
+    if (j.N * std::log2(q) < 40.0)
+        K = std::min(K, std::pow(q, (double)j.N));
+    return (double)j.S * j.T * K * (4.0 * j.N * (j.N - 1) + 11.0 * j.N) * 1e-9;
 }
 
 class Scheduler {
   public:
     Scheduler(const mpnl_server_config &cfg, Executor &ex) : cfg_(cfg), ex_(ex) {}
 
-    void submit(const Job &j, std::vector<mpnl_completion> &out)
+    double estimate(double gflop) const { return cfg_.est_fixed_us + cfg_.est_us_per_gflop * gflop; }
+
+    // Queue a submitted job as its pieces (one piece when it is not split).
+    void submit(int64_t id, double arrival, std::vector<Job> pieces, std::vector<mpnl_completion> &out)
     {
-        const bool too_big = cfg_.hbm_budget != 0 && j.bytes > cfg_.hbm_budget;
-        const bool full = cfg_.max_queue > 0 && (int)wait_.size() >= cfg_.max_queue;
-        if (too_big || full) {
+        bool too_big = false;
+        for (const Job &p : pieces)
+            too_big |= cfg_.hbm_budget != 0 && p.bytes > cfg_.hbm_budget;
+        const bool full = cfg_.max_queue > 0 && queued_jobs_ >= cfg_.max_queue;
+        if (too_big || full || pieces.empty()) {
             const double t = ex_.now();
-            out.push_back(make_completion(j, MPNL_JOB_REJECTED, MPNL_OK, t, t));
+            out.push_back(make_completion(id, arrival, MPNL_JOB_REJECTED, MPNL_OK, t, t));
             return;
         }
-        wait_.push_back(j);
+        const int pi = new_parent();
+        Parent &P = parents_[pi];
+        P = Parent{};
+        P.id = id;
+        P.arrival = arrival;
+        P.left = (int)pieces.size();
+        P.waiting = (int)pieces.size();
+        P.live = true;
+        for (Job &p : pieces) {
+            p.parent = pi;
+            P.est_left += p.est_us;
+            wait_.push_back(p);
+        }
+        ++queued_jobs_;
+        ++open_jobs_;
     }
 
-    // Retire finished launches, then admit waiting jobs into new launches
-    // while launch slots and budget allow.  The queue is served in arrival
-    // order: a head job that does not fit the budget waits for memory to be
-    // freed and blocks the jobs behind it.
+    // Retire finished launches, then admit waiting pieces into new launches
+    // while launch slots and budget allow.
     void progress(std::vector<mpnl_completion> &out)
     {
         for (size_t i = 0; i < flights_.size();) {
@@ -85,62 +120,164 @@ class Scheduler {
                 continue;
             }
             for (const Job &j : f.jobs)
-                out.push_back(make_completion(j, err == MPNL_OK ? MPNL_JOB_DONE : MPNL_JOB_FAILED, err, f.start, done));
+                piece_done(j.parent, err, done, out);
             held_ -= f.bytes;
-            running_ -= (int)f.jobs.size();
             ex_.release(f.token);
             flights_.erase(flights_.begin() + (long)i);
         }
         while ((int)flights_.size() < cfg_.max_inflight && !wait_.empty()) {
             const double t = ex_.now();
+            if (cfg_.drop_late)
+                drop_late(t, out);
+            if (wait_.empty())
+                break;
+            order(t);
             std::vector<Job> batch;
             size_t bytes = 0;
-            while (!wait_.empty() && (int)batch.size() < cfg_.max_batch_jobs) {
-                const Job &h = wait_.front();
-                if (cfg_.drop_late && t - h.arrival > cfg_.deadline_us) {
-                    out.push_back(make_completion(h, MPNL_JOB_DROPPED, MPNL_OK, t, t));
-                    wait_.pop_front();
-                    continue;
-                }
+            size_t k = 0;
+            while (k < wait_.size() && (int)batch.size() < cfg_.max_batch_jobs) {
+                const Job &h = wait_[k];
                 if (cfg_.hbm_budget != 0 && held_ + bytes + h.bytes > cfg_.hbm_budget)
-                    break;
+                    break;  // waits for memory and blocks the pieces behind it
                 bytes += h.bytes;
                 batch.push_back(h);
-                wait_.pop_front();
+                ++k;
             }
             if (batch.empty())
                 break;
+            wait_.erase(wait_.begin(), wait_.begin() + (long)k);
+            for (const Job &j : batch) {
+                Parent &P = parents_[j.parent];
+                P.est_left -= j.est_us;
+                --P.waiting;
+                if (P.start < 0.0) {
+                    P.start = t;
+                    --queued_jobs_;
+                }
+            }
             const int tok = ex_.launch(batch);
             ++launches_;
             if (tok < 0) {
                 const double te = ex_.now();
                 for (const Job &j : batch)
-                    out.push_back(make_completion(j, MPNL_JOB_FAILED, tok, t, te));
+                    piece_done(j.parent, tok, te, out);
                 continue;
             }
             held_ += bytes;
-            running_ += (int)batch.size();
             flights_.push_back(Flight{tok, std::move(batch), t, bytes});
         }
     }
 
-    int pending() const { return (int)wait_.size() + running_; }
+    int pending() const { return open_jobs_; }
     int launches() const { return launches_; }
     bool idle() const { return flights_.empty() && wait_.empty(); }
 
   private:
+    struct Parent {
+        int64_t id = 0;
+        double arrival = 0.0;
+        int left = 0;         // pieces not yet finished
+        int waiting = 0;      // pieces not yet admitted
+        double est_left = 0;  // estimated time of the pieces not yet admitted
+        double start = -1.0;  // first admission
+        double done = 0.0;    // latest piece completion
+        int error = MPNL_OK;
+        bool live = false;
+    };
     struct Flight {
         int token;
         std::vector<Job> jobs;
         double start;
         size_t bytes;
     };
+
+    int new_parent()
+    {
+        if (!free_.empty()) {
+            const int i = free_.back();
+            free_.pop_back();
+            return i;
+        }
+        parents_.emplace_back();
+        return (int)parents_.size() - 1;
+    }
+
+    void finish_parent(int pi, int status, std::vector<mpnl_completion> &out)
+    {
+        Parent &P = parents_[pi];
+        out.push_back(make_completion(P.id, P.arrival, status, P.error, P.start, P.done));
+        P.live = false;
+        free_.push_back(pi);
+        --open_jobs_;
+    }
+
+    void piece_done(int pi, int err, double done, std::vector<mpnl_completion> &out)
+    {
+        Parent &P = parents_[pi];
+        P.done = std::max(P.done, done);
+        if (err != MPNL_OK && P.error == MPNL_OK)
+            P.error = err;
+        if (--P.left == 0)
+            finish_parent(pi, P.error == MPNL_OK ? MPNL_JOB_DONE : MPNL_JOB_FAILED, out);
+    }
+
+    // A job that has waited past the deadline and has no piece running or
+    // done yet is dropped with all its pieces.
+    void drop_late(double t, std::vector<mpnl_completion> &out)
+    {
+        std::vector<int> gone;
+        for (const Job &j : wait_) {
+            const Parent &P = parents_[j.parent];
+            if (P.start < 0.0 && t - P.arrival > cfg_.deadline_us &&
+                std::find(gone.begin(), gone.end(), j.parent) == gone.end())
+                gone.push_back(j.parent);
+        }
+        if (gone.empty())
+            return;
+        wait_.erase(std::remove_if(wait_.begin(), wait_.end(),
+                                   [&](const Job &j) {
+                                       return std::find(gone.begin(), gone.end(), j.parent) != gone.end();
+                                   }),
+                    wait_.end());
+        for (int pi : gone) {
+            Parent &P = parents_[pi];
+            P.start = t;
+            P.done = t;
+            --queued_jobs_;
+            finish_parent(pi, MPNL_JOB_DROPPED, out);
+        }
+    }
+
+    // Admission order of the waiting pieces (stable: arrival order, then
+    // piece order, breaks every tie).
+    void order(double t)
+    {
+        if (cfg_.policy != MPNL_SCHED_SLACK)
+            return;
+        std::stable_sort(wait_.begin(), wait_.end(), [&](const Job &a, const Job &b) {
+            const Parent &A = parents_[a.parent], &B = parents_[b.parent];
+            const double sa = A.arrival + cfg_.deadline_us - t - A.est_left;
+            const double sb = B.arrival + cfg_.deadline_us - t - B.est_left;
+            const bool fa = sa >= 0.0, fb = sb >= 0.0;
+            if (fa != fb)
+                return fa;                        // jobs that can still make it first
+            if (fa && sa != sb)
+                return sa < sb;                   // least slack first
+            if (a.arrival != b.arrival)
+                return a.arrival < b.arrival;     // then arrival order
+            return a.parent == b.parent && a.s0 < b.s0;
+        });
+    }
+
     mpnl_server_config cfg_;
     Executor &ex_;
     std::deque<Job> wait_;
     std::vector<Flight> flights_;
+    std::vector<Parent> parents_;
+    std::vector<int> free_;
     size_t held_ = 0;
-    int running_ = 0;
+    int queued_jobs_ = 0;  // submitted jobs none of whose pieces was admitted yet
+    int open_jobs_ = 0;    // submitted jobs not yet completed
     int launches_ = 0;
 };
 
@@ -159,6 +296,8 @@ class GpuExecutor : public Executor {
         streams_.assign(n_, nullptr);
         done_.assign(n_, nullptr);
         busy_.assign(n_, false);
+        tmp_.assign(n_, nullptr);
+        cap_.assign(n_, 0);
         int prev = -1;
         (void)hipGetDevice(&prev);
         hipError_t e = hipSetDevice(device_);
@@ -196,6 +335,9 @@ class GpuExecutor : public Executor {
         }
         if (ref_)
             (void)hipEventDestroy(ref_);
+        for (void *b : tmp_)
+            if (b)
+                (void)hipFree(b);
         if (prev >= 0)
             (void)hipSetDevice(prev);
     }
@@ -205,6 +347,11 @@ class GpuExecutor : public Executor {
         return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0_).count();
     }
 
+    // A piece of a split job reads its subcarriers of y and writes those of
+    // out, which are strided in the job's (T, S, .) arrays: its y rows are
+    // gathered into the launch slot's staging buffer before the launch and
+    // its decisions scattered back after it (device-to-device copies on the
+    // slot's stream).
     int launch(const std::vector<Job> &jobs) override
     {
         int k = 0;
@@ -212,16 +359,63 @@ class GpuExecutor : public Executor {
             ++k;
         if (k == n_)
             return MPNL_E_INVAL;  // the scheduler keeps at most n_ launches
+        hipStream_t st = streams_[k];
+        size_t need = 0;
+        for (const Job &j : jobs)
+            if (j.s_full)
+                need += staging_bytes(j.job);
+        if (need > cap_[k]) {  // the slot is idle: nothing of it is in flight
+            if (tmp_[k])
+                (void)hipFree(tmp_[k]);
+            tmp_[k] = nullptr;
+            cap_[k] = 0;
+            if (hipMalloc(&tmp_[k], need) != hipSuccess)
+                return MPNL_E_NOMEM;
+            cap_[k] = need;
+        }
         std::vector<mpnl_job> js(jobs.size());
-        for (size_t i = 0; i < jobs.size(); ++i)
-            js[i] = jobs[i].job;
-        const int rc = mpnl_detect_batch(ctx_, js.data(), (int)js.size(), streams_[k]);
+        char *at = (char *)tmp_[k];
+        for (size_t i = 0; i < jobs.size(); ++i) {
+            const Job &j = jobs[i];
+            js[i] = j.job;
+            if (!j.s_full)
+                continue;
+            const mpnl_job &w = j.job;  // H / y / out of the whole job, S = the piece's
+            const size_t yrow = (size_t)w.S * w.M * sizeof(float2), orow = (size_t)w.S * w.N * sizeof(int32_t);
+            js[i].H = (const float2 *)w.H + (size_t)j.s0 * w.M * w.N;
+            js[i].y = at;
+            js[i].out = (int32_t *)(at + align_up(w.T * yrow));
+            if (hipMemcpy2DAsync(at, yrow, (const float2 *)w.y + (size_t)j.s0 * w.M,
+                                 (size_t)j.s_full * w.M * sizeof(float2), yrow, w.T, hipMemcpyDeviceToDevice,
+                                 st) != hipSuccess)
+                return MPNL_E_HIP;
+            at += staging_bytes(w);
+        }
+        const int rc = mpnl_detect_batch(ctx_, js.data(), (int)js.size(), st);
         if (rc != MPNL_OK)
             return rc;
-        if (hipEventRecord(done_[k], streams_[k]) != hipSuccess)
+        for (size_t i = 0; i < jobs.size(); ++i) {
+            const Job &j = jobs[i];
+            if (!j.s_full)
+                continue;
+            const mpnl_job &w = j.job;
+            const size_t orow = (size_t)w.S * w.N * sizeof(int32_t);
+            if (hipMemcpy2DAsync(w.out + (size_t)j.s0 * w.N, (size_t)j.s_full * w.N * sizeof(int32_t), js[i].out,
+                                 orow, orow, w.T, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return MPNL_E_HIP;
+        }
+        if (hipEventRecord(done_[k], st) != hipSuccess)
             return MPNL_E_HIP;
         busy_[k] = true;
         return k;
+    }
+
+    static size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+    // staging of one piece: its y rows, then its decisions
+    static size_t staging_bytes(const mpnl_job &piece)
+    {
+        return align_up((size_t)piece.T * piece.S * piece.M * sizeof(float2)) +
+               align_up((size_t)piece.T * piece.S * piece.N * sizeof(int32_t));
     }
 
     int finished(int token, double *done, int *error) override
@@ -250,6 +444,8 @@ class GpuExecutor : public Executor {
     std::vector<hipStream_t> streams_;
     std::vector<hipEvent_t> done_;
     std::vector<bool> busy_;
+    std::vector<void *> tmp_;   // per launch slot: staging of split pieces
+    std::vector<size_t> cap_;
     hipEvent_t ref_ = nullptr;
     double ref_us_ = 0.0;
 };
@@ -314,7 +510,56 @@ class SimExecutor : public Executor {
 bool config_ok(const mpnl_server_config *c)
 {
     return c && c->max_batch_jobs >= 1 && c->max_inflight >= 1 && c->max_inflight <= 8 && c->max_queue >= 0 &&
-           c->deadline_us >= 0.0;
+           c->deadline_us >= 0.0 && (c->policy == MPNL_SCHED_FIFO || c->policy == MPNL_SCHED_SLACK) &&
+           c->split_vectors >= 0 && std::isfinite(c->est_fixed_us) && std::isfinite(c->est_us_per_gflop);
+}
+
+// A device job as its pieces: whole subcarrier ranges of at most
+// max(T, split_vectors) vectors when it has more than split_vectors, else
+// one piece.  A piece carries the whole job's H / y / out and its own S; its
+// bytes add the staging of its y rows and decisions.
+std::vector<Job> device_pieces(const Scheduler &sch, const mpnl_server_config &cfg, const mpnl_job &job, int64_t id,
+                               double arrival)
+{
+    std::vector<Job> out;
+    const int64_t vec = (int64_t)job.S * job.T;
+    if (cfg.split_vectors <= 0 || vec <= cfg.split_vectors) {
+        out.push_back(Job{id, arrival, job_device_bytes(job), vec, sch.estimate(job_gflop(job)), job});
+        return out;
+    }
+    const int per = (int)std::max<int64_t>(1, cfg.split_vectors / job.T);  // subcarriers a piece
+    const int n = (job.S + per - 1) / per;
+    for (int i = 0; i < n; ++i) {
+        const int s0 = (int)((int64_t)job.S * i / n), s1 = (int)((int64_t)job.S * (i + 1) / n);
+        mpnl_job p = job;
+        p.S = s1 - s0;
+        Job j{id, arrival, job_device_bytes(p) + GpuExecutor::staging_bytes(p), (int64_t)p.S * p.T,
+              sch.estimate(job_gflop(p)), p};
+        j.s0 = s0;
+        j.s_full = job.S;
+        out.push_back(j);
+    }
+    return out;
+}
+
+// A modelled job as its pieces: near-equal vector counts, bytes and work
+// shared in proportion.
+std::vector<Job> sim_pieces(const Scheduler &sch, const mpnl_server_config &cfg, const mpnl_sim_job &sj)
+{
+    std::vector<Job> out;
+    const int64_t n = (cfg.split_vectors > 0 && sj.vectors > cfg.split_vectors)
+                          ? (sj.vectors + cfg.split_vectors - 1) / cfg.split_vectors
+                          : 1;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t v0 = sj.vectors * i / n, v1 = sj.vectors * (i + 1) / n;
+        const double f = sj.vectors > 0 ? (double)(v1 - v0) / (double)sj.vectors : 1.0 / (double)n;
+        Job j{sj.id, sj.arrival_us, (size_t)std::ceil((double)sj.bytes * f), v1 - v0, sch.estimate(sj.gflop * f),
+              mpnl_job{}};
+        j.s0 = (int)i;
+        j.s_full = n > 1 ? 1 : 0;
+        out.push_back(j);
+    }
+    return out;
 }
 
 // splitmix64: seeded stream of uniform 64-bit words
@@ -398,8 +643,7 @@ int mpnl_server_submit(mpnl_server *s, const mpnl_job *job, int64_t id, double a
     const int rc = mpnl::validate_job_shape(*job);
     if (rc != MPNL_OK)
         return rc;
-    mpnl::serve::Job j{id, arrival_us, mpnl::job_device_bytes(*job), (int64_t)job->S * job->T, *job};
-    s->sched->submit(j, s->ready);
+    s->sched->submit(id, arrival_us, mpnl::serve::device_pieces(*s->sched, s->cfg, *job, id, arrival_us), s->ready);
     return MPNL_OK;
 }
 
@@ -428,14 +672,12 @@ int mpnl_server_run_poisson(mpnl_server *s, const mpnl_job *pool, int pool_n, in
     if (!s || !pool || pool_n <= 0 || n_jobs < 0 || !(rate_hz > 0.0) || (n_jobs > 0 && !out) ||
         !s->sched->idle() || !s->ready.empty())
         return MPNL_E_INVAL;
-    std::vector<size_t> bytes(pool_n);
     for (int p = 0; p < pool_n; ++p) {
         if (!pool[p].H || !pool[p].y || !pool[p].out)
             return MPNL_E_INVAL;
         const int rc = mpnl::validate_job_shape(pool[p]);
         if (rc != MPNL_OK)
             return rc;
-        bytes[p] = mpnl::job_device_bytes(pool[p]);
     }
     uint64_t rng = seed;
     std::vector<char> seen(n_jobs, 0);
@@ -448,8 +690,7 @@ int mpnl_server_run_poisson(mpnl_server *s, const mpnl_job *pool, int pool_n, in
             const int p = (int)(splitmix64(rng) % (uint64_t)pool_n);
             if (entry)
                 entry[submitted] = p;
-            Job j{submitted, t_next, bytes[p], (int64_t)pool[p].S * pool[p].T, pool[p]};
-            s->sched->submit(j, got);
+            s->sched->submit(submitted, t_next, device_pieces(*s->sched, s->cfg, pool[p], submitted, t_next), got);
             ++submitted;
             t_next += exp_gap_us(rng, rate_hz);
         }
@@ -492,8 +733,7 @@ int mpnl_sched_simulate(const mpnl_server_config *cfg, const mpnl_sim_device *de
     while (completed < n_jobs) {
         while (next < n_jobs && jobs[next].arrival_us <= ex.clock) {
             const mpnl_sim_job &sj = jobs[next];
-            Job j{sj.id, sj.arrival_us, sj.bytes, sj.vectors, mpnl_job{}};
-            sched.submit(j, got);
+            sched.submit(sj.id, sj.arrival_us, sim_pieces(sched, *cfg, sj), got);
             ++next;
         }
         sched.progress(got);

@@ -71,8 +71,12 @@ def test_plan_replays_equal_alone(ctx, autotune):
         shapes = plan.launch_shapes()
         assert len(shapes) == len({(N, b, (min(K, (1 << b) ** N) + 63) // 64)
                                    for S, T, M, N, b, K in SMALL})
-        assert all(x["vectors_per_workgroup"] in (1, 2, 4) and x["lanes"] * x["vectors_per_workgroup"] <= 256
-                   for x in shapes)
+        assert all(x["items_per_workgroup"] in (1, 2, 4) and x["group_lanes"] % 64 == 0
+                   and x["lanes"] % x["group_lanes"] == 0
+                   and x["group_lanes"] * x["items_per_workgroup"] <= 256 for x in shapes)
+        if not autotune:  # the default shape: one-wavefront path groups, group major, four per workgroup
+            assert all(x["group_lanes"] == 64 and x["items_per_workgroup"] == 4 and x["group_major"] == 1
+                       for x in shapes)
         # oracle parity on one job of the last replay
         sl, got = slots[1], jobs[1]["out"].cpu().numpy()
         ref, diag = oracle.detect_slot("mpnl", sl.H, sl.y, sl.bits, n_paths=SMALL[1][5],

@@ -184,3 +184,110 @@ def test_antenna_search_takes_the_first_count_meeting_the_target():
     assert M == 10 and calls == list(range(2, 11)) and trace[-1] == (10, 0.1)
     M, trace = bench.antenna_search(lambda m: 1.0, 3, 6, 0.5)
     assert M is None and [m for m, _ in trace] == [3, 4, 5, 6]
+
+
+# ---- pieces of split jobs and the slack policy ----------------------------
+SLACK = mp.MPNL_SCHED_SLACK
+
+
+def test_split_job_completes_with_its_last_piece():
+    cfg = mp.server_config(max_batch_jobs=1, max_inflight=1, split_vectors=2500)
+    jobs = [dict(arrival_us=0.0, bytes=4000, vectors=10000)]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=10.0, per_vector_us=0.01)
+    _check_invariants(jobs, comp)
+    assert nl == 4  # four pieces of 2500 vectors, one launch each
+    assert comp[0]["status"] == DONE
+    assert comp[0]["start_us"] == pytest.approx(0.0)
+    assert comp[0]["done_us"] == pytest.approx(4 * (10.0 + 25.0))
+
+
+def test_uneven_split_covers_every_vector():
+    cfg = mp.server_config(max_batch_jobs=8, max_inflight=1, split_vectors=3000)
+    jobs = [dict(arrival_us=0.0, bytes=100, vectors=10001)]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=0.0, per_vector_us=1.0)
+    assert nl == 1  # four pieces, all in one launch
+    assert comp[0]["done_us"] == pytest.approx(10001.0)
+
+
+@pytest.mark.parametrize("policy", [mp.MPNL_SCHED_FIFO, SLACK])
+def test_small_job_between_pieces_of_a_large_one(policy):
+    """A large job split into eight pieces arrives first, a small job right
+    after.  Under the slack policy the small job (which can still meet the
+    deadline) runs after the first piece; in arrival order it waits for all
+    eight."""
+    cfg = mp.server_config(max_batch_jobs=1, max_inflight=1, split_vectors=5000, policy=policy,
+                           est_fixed_us=10.0, est_us_per_gflop=1.0)
+    jobs = [dict(arrival_us=0.0, bytes=1, vectors=40000, gflop=4000.0),
+            dict(arrival_us=1.0, bytes=1, vectors=1000, gflop=10.0)]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=10.0, per_vector_us=0.01)
+    _check_invariants(jobs, comp)
+    assert nl == 9
+    piece = 10.0 + 50.0
+    if policy == SLACK:
+        assert comp[1]["start_us"] == pytest.approx(piece)
+        assert comp[1]["done_us"] == pytest.approx(piece + 20.0)
+        assert comp[0]["done_us"] == pytest.approx(8 * piece + 20.0)
+    else:
+        assert comp[1]["start_us"] == pytest.approx(8 * piece)
+        assert comp[0]["done_us"] == pytest.approx(8 * piece)
+
+
+def test_slack_takes_the_most_urgent_feasible_job_first():
+    """While the device is busy, B (little work) and then A (much work)
+    arrive; when it frees up A has less slack and goes first, although it
+    arrived later."""
+    cfg = mp.server_config(max_batch_jobs=1, max_inflight=1, policy=SLACK, deadline_us=500.0,
+                           est_fixed_us=10.0, est_us_per_gflop=1.0)
+    jobs = [dict(arrival_us=0.0, vectors=9000, gflop=90.0),     # X: occupies the device until 100
+            dict(arrival_us=10.0, vectors=4000, gflop=40.0),    # B: slack at 100 is 360
+            dict(arrival_us=20.0, vectors=39000, gflop=390.0)]  # A: slack at 100 is 20
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=10.0, per_vector_us=0.01)
+    _check_invariants(jobs, comp)
+    assert comp[2]["start_us"] == pytest.approx(100.0)
+    assert comp[2]["done_us"] == pytest.approx(500.0)
+    assert comp[1]["start_us"] == pytest.approx(500.0)
+    cfg.policy = mp.MPNL_SCHED_FIFO
+    comp, _ = mp.mpnl_sched_simulate(cfg, jobs, launch_us=10.0, per_vector_us=0.01)
+    assert comp[1]["start_us"] == pytest.approx(100.0)
+
+
+def test_jobs_that_cannot_meet_the_deadline_go_last():
+    cfg = mp.server_config(max_batch_jobs=1, max_inflight=1, policy=SLACK, deadline_us=500.0,
+                           est_fixed_us=10.0, est_us_per_gflop=1.0)
+    jobs = [dict(arrival_us=0.0, vectors=100, gflop=0.0),        # occupies the device until 11
+            dict(arrival_us=1.0, vectors=100000, gflop=990.0),   # C: estimated 1000 us, infeasible
+            dict(arrival_us=2.0, vectors=1000, gflop=10.0),      # D: feasible
+            dict(arrival_us=3.0, vectors=100000, gflop=990.0)]   # E: infeasible, after C
+    comp, _ = mp.mpnl_sched_simulate(cfg, jobs, launch_us=10.0, per_vector_us=0.01)
+    _check_invariants(jobs, comp)
+    assert comp[2]["start_us"] < comp[1]["start_us"] < comp[3]["start_us"]
+    assert all(c["status"] == DONE for c in comp)
+
+
+def test_drop_late_spares_a_job_whose_pieces_have_started():
+    cfg = mp.server_config(max_batch_jobs=1, max_inflight=1, split_vectors=1000, drop_late=True,
+                           deadline_us=100.0)
+    jobs = [dict(arrival_us=0.0, vectors=4000),   # four pieces of 80 us: runs past the deadline
+            dict(arrival_us=1.0, vectors=100)]    # waits 320 us: dropped
+    comp, _ = mp.mpnl_sched_simulate(cfg, jobs, launch_us=0.0, per_vector_us=0.08)
+    _check_invariants(jobs, comp)
+    assert comp[0]["status"] == DONE and comp[0]["done_us"] == pytest.approx(320.0)
+    assert comp[1]["status"] == DROP
+
+
+def test_budget_counts_pieces():
+    """Pieces are admitted against the budget one by one: a job twice the
+    budget runs when split into pieces that fit."""
+    cfg = mp.server_config(hbm_budget=1000, max_batch_jobs=8, max_inflight=4, split_vectors=500)
+    jobs = [dict(arrival_us=0.0, bytes=2000, vectors=2000)]
+    comp, nl = mp.mpnl_sched_simulate(cfg, jobs, launch_us=1.0, per_vector_us=0.0)
+    assert comp[0]["status"] == DONE and nl >= 2
+    cfg.split_vectors = 0
+    comp, _ = mp.mpnl_sched_simulate(cfg, jobs, launch_us=1.0, per_vector_us=0.0)
+    assert comp[0]["status"] == REJ
+
+
+def test_bad_policy_config_is_rejected():
+    for cfg in (mp.server_config(policy=7), mp.server_config(split_vectors=-1)):
+        with pytest.raises(mp.MpnlError):
+            mp.mpnl_sched_simulate(cfg, [dict(arrival_us=0.0, vectors=1)])
