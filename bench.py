@@ -29,6 +29,7 @@ if ROOT not in sys.path:
 
 METRIC = "detected vectors/s & p99 slot latency at matched BER vs plain FP32 kernel"
 PEAK_FP32_TFLOPS = 157.3  # MI355X fp32 vector: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+VALU_ISSUE_PER_S = 256 * 2.4e9  # wave64 VALU instructions: one per CU per cycle (4 SIMD x 16 lanes)
 
 # name -> (users N, antennas M, bits, subcarriers S, symbols T, snr dB, channel, default paths)
 WORKLOADS = {
@@ -52,6 +53,16 @@ SWEEP_WORKLOAD = "16x16-qam16-S1200-T14-snr-sweep"
 # antenna search, Sec. III-B, without coding): regularised MPNL (64 / 256
 # paths, overloaded slots allowed) and linear MMSE, 16-QAM, 20 dB
 ANTENNA_WORKLOAD = "antenna-search-qam16-20dB"
+# VALU issue rate of the device for three instruction mixes (the ceiling the
+# path search's counters are set against)
+PROBE_WORKLOAD = "valu-issue-probe"
+# VALU wave-instructions per round of the probe kernel, from its gfx950
+# assembly (loop counter and branch are scalar) and confirmed by the
+# SQ_INSTS_VALU counter: eight v_fma_f32; the mix: 4 x (v_rndne, v_med3, v_sub,
+# v_mul, v_cmp, v_cndmask) and 4 register moves; DPP: eight v_mov_b32_dpp,
+# eight moves of the bound-control zero and eight s_nop hazard waits, which
+# the counter takes as VALU (24)
+PROBE_VALU_PER_ROUND = {0: 8, 1: 28, 2: 24}
 
 
 def _counter_summary(name: str):
@@ -90,16 +101,21 @@ def measured_traffic(workload: str, K: int, precision: str):
         return None
 
 
-def measured_multi_counters():
-    """(HBM bytes, executed FP32 FMA flops) of the path-search launches of one
-    40-cell FP16 batch from the committed counter summary, or (None, None)."""
+def measured_multi_counters(precision: str):
+    """Counter figures of the path-search launches (search + group
+    reduction) of one 40-cell FP16 batch from the committed summary: HBM
+    bytes, VALU wave-instructions, FP32 FMA wave-instructions; None for
+    another precision or once the kernel's sources changed."""
+    if precision != "fp16":
+        return None
     kv = _counter_summary("counters_path_search_multi_cells40-fp16.txt")
     if not kv:
-        return None, None
+        return None
     try:
-        return float(kv["traffic_bytes_per_step"]), float(kv["executed_fma_flops_per_step"])
+        return {k: float(kv[k]) for k in ("traffic_bytes_per_step", "valu_wave_insts_per_step",
+                                          "fma_f32_wave_insts_per_step", "trace_path_ms_per_step")}
     except (KeyError, ValueError):
-        return None, None
+        return None
 
 
 def path_flops_per_vector(N: int, K: int) -> int:
@@ -140,7 +156,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=CELLS_WORKLOAD,
                     choices=sorted(WORKLOADS) + [CELLS_WORKLOAD, SERVING_WORKLOAD, SWEEP_WORKLOAD,
-                                                 ANTENNA_WORKLOAD])
+                                                 ANTENNA_WORKLOAD, PROBE_WORKLOAD])
     ap.add_argument("--rate", type=float, default=20000.0, help="serving: offered jobs/s")
     ap.add_argument("--jobs", type=int, default=2000, help="serving: jobs per run")
     ap.add_argument("--no-autotune", action="store_true", help="batch workload: default grid sizes")
@@ -165,6 +181,8 @@ def main() -> int:
         return run_sweep(args)
     if args.workload == ANTENNA_WORKLOAD:
         return run_antenna_search(args)
+    if args.workload == PROBE_WORKLOAD:
+        return run_probe(args)
 
     import numpy as np
     import torch
@@ -364,6 +382,12 @@ def run_cells(args) -> int:
     nbits_tx = sum(sl.s_idx.size * sl.bits for sl in slots)
     ctx = mp.Context(0)
     ctx.set_precision(PRECISIONS[prec])
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     plan = ctx.batch_plan([dict(S=c.S, T=T, M=c.M, N=c.N, mod=c.bits, n_paths=c.n_paths) for c in cells],
                           autotune=not args.no_autotune)
     stream = torch.cuda.current_stream()
@@ -496,17 +520,23 @@ def run_cells(args) -> int:
         mism["plain_fp32"] += int(np.any(gp[:, :n_sub] != ref, axis=-1).sum())
         nv_or += ref.shape[0] * ref.shape[1]
 
-    traffic, executed = measured_multi_counters()
+    cnt = measured_multi_counters(prec)
     roof = {"bound": "alu", "kernel": "path_search_multi_kernel", "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": traffic, "achieved_is": "algorithmic flops of all N_p paths per batch / path-search "
-                                                "kernel time per batch (an effective rate: pruning skips work)",
+            "traffic": cnt["traffic_bytes_per_step"] if cnt else None,
+            "achieved_is": "algorithmic flops of all N_p paths per batch / path-search time per batch (the 38 "
+                           "path-search launches and their group reductions, HIP events on the launch stream); "
+                           "an effective rate, pruning skips work",
             "flops_per_step": flops_run, "path_ms_per_step": path_ms_step,
             "path_launches_per_step": paths_n / n_prof}
-    if executed is not None:
-        ex = executed / (path_ms_step * 1e-3) / 1e12
-        roof["executed_fma_tflops"] = ex
-        roof["executed_frac_of_nonpacked_fp32"] = ex / (PEAK_FP32_TFLOPS / 2)
+    if cnt:
+        # executed work from the committed counters of the same launches
+        path_s = path_ms_step * 1e-3
+        roof["valu_issue_frac"] = cnt["valu_wave_insts_per_step"] / (VALU_ISSUE_PER_S * path_s)
+        roof["valu_issue_is"] = ("VALU wave64 instructions per batch (counters) / (256 CUs x 1 per cycle x "
+                                 "2.4 GHz x path time)")
+        roof["executed_fma_f32_tflops"] = cnt["fma_f32_wave_insts_per_step"] * 128 / path_s / 1e12
+        roof["rocprof_path_ms_per_step"] = cnt["trace_path_ms_per_step"]
     res = {
         "metric": METRIC, "value": value, "unit": "vectors/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
@@ -621,6 +651,30 @@ def run_antenna_search(args) -> int:
     return 0
 
 
+def run_probe(args) -> int:
+    """VALU wave-instructions per CU per cycle (2.4 GHz) for long independent
+    chains: FMA, the point-choice mix, DPP lane moves."""
+    import torch
+
+    import paper_2409_14355_amd as mp
+    torch.cuda.init()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    waves, iters = cus * 4 * 8, 20000  # eight wavefronts per SIMD
+    rate = {}
+    for kind, name in ((0, "fma_f32"), (1, "point_choice_mix"), (2, "dpp_move")):
+        ms = mp.mpnl_diag_valu_rate(0, kind, waves, iters)
+        insts = waves * iters * PROBE_VALU_PER_ROUND[kind]
+        rate[name] = {"ms": ms, "valu_wave_insts": insts,
+                      "per_cu_cycle_at_2p4GHz": insts / (cus * 2.4e9 * ms * 1e-3)}
+    res = {"metric": "VALU wave64 instructions per CU per cycle", "value": rate["fma_f32"]["per_cu_cycle_at_2p4GHz"],
+           "unit": "instructions/CU/cycle", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": None,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": PROBE_WORKLOAD, "compute_units": cus, "waves": waves, "rounds": iters},
+           "rates": rate}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def run_sweep(args) -> int:
     """BER against SNR (10..24 dB) for MPNL with 64 and 256 paths on 16x16,
     and linear MMSE with 16, 32 and 48 antennas for the same 16 users; up to
@@ -721,10 +775,10 @@ def _serving_stats(comp, vec_of, floor_of=None):
 def run_serving(args) -> int:
     """Poisson arrivals through the continuous-batching server, FP32 and FP16
     path metrics: every pool job's latency alone (which calibrates the slack
-    policy's service-time model), the closed-loop capacity, then the offered
-    rate (overload) and 70% of the capacity, under the slack policy with
-    large jobs split into pieces and, for comparison, in arrival order
-    without splitting."""
+    policy's service-time model), the closed-loop capacity of each admission
+    variant (arrival order; least slack; least slack with jobs above 25 k
+    vectors split into pieces), each variant at 70% of the arrival-order
+    capacity, and the offered rate (overload, late jobs dropped)."""
     import numpy as np
     import torch
 
@@ -746,7 +800,7 @@ def run_serving(args) -> int:
     ctx = mp.Context(0)
     stream = torch.cuda.current_stream()
     seed = 31
-    split = 8000  # vectors per piece of a split job
+    split = 25000  # vectors per piece of a split job (about the mean job)
 
     def alone_us(prec, reps=3):
         ctx.set_precision(prec)
@@ -766,14 +820,12 @@ def run_serving(args) -> int:
     def stats(comp):
         return _serving_stats(comp, lambda c: cells[c["entry"]].S * T, lambda c: floor_ms[c["entry"]])
 
-    def cfg_of(policy, est, rate_cap=False, drop=True):
+    def cfg_of(policy, est, split_at=0, drop=True):
         a, b = est
-        if policy == "slack":
-            return mp.server_config(hbm_budget=16 << 30, max_batch_jobs=8, max_inflight=3, max_queue=256,
-                                    deadline_us=500.0, drop_late=drop, policy=mp.MPNL_SCHED_SLACK,
-                                    split_vectors=split, est_fixed_us=a, est_us_per_gflop=b)
         return mp.server_config(hbm_budget=16 << 30, max_batch_jobs=8, max_inflight=3, max_queue=256,
-                                deadline_us=500.0, drop_late=drop)
+                                deadline_us=500.0, drop_late=drop,
+                                policy=mp.MPNL_SCHED_SLACK if policy == "slack" else mp.MPNL_SCHED_FIFO,
+                                split_vectors=split_at, est_fixed_us=a, est_us_per_gflop=b)
 
     def run(cfg, rate, n_jobs, prec):
         nonlocal seed
@@ -800,31 +852,32 @@ def run_serving(args) -> int:
         torch.cuda.synchronize()
         return len(comp) / ((max(c["done_us"] for c in comp) - t0) * 1e-6)
 
+    # admission variants compared at the same offered load
+    variants = {"fifo": ("fifo", 0), "slack": ("slack", 0), "slack_split": ("slack", split)}
     res_runs = {}
     for prec, name in ((0, "fp32"), (1, "fp16")):
         lat = alone_us(prec)
         A = np.stack([np.ones_like(gflop), gflop], axis=1)
         est = tuple(float(x) for x in np.linalg.lstsq(A, lat, rcond=None)[0])
         est = (max(est[0], 0.0), max(est[1], 0.0))
-        run(cfg_of("slack", est), 2000.0, 50, prec)  # warm-up
-        cap = capacity(cfg_of("slack", est, drop=False), prec)
-        cap_fifo = capacity(cfg_of("fifo", est, drop=False), prec)
-        offered = stats(run(cfg_of("slack", est), args.rate, args.jobs, prec))
-        sus_rate = 0.7 * cap
+        run(cfg_of("fifo", est), 2000.0, 50, prec)  # warm-up
+        caps = {v: capacity(cfg_of(pol, est, sp, drop=False), prec) for v, (pol, sp) in variants.items()}
+        sus_rate = 0.7 * caps["fifo"]
         n_sus = max(300, int(sus_rate * 0.3))
-        sustained = stats(run(cfg_of("slack", est, drop=False), sus_rate, n_sus, prec))
-        sustained_fifo = stats(run(cfg_of("fifo", est, drop=False), sus_rate, n_sus, prec))
+        at70 = {v: stats(run(cfg_of(pol, est, sp, drop=False), sus_rate, n_sus, prec))
+                for v, (pol, sp) in variants.items()}
+        offered = stats(run(cfg_of("fifo", est), args.rate, args.jobs, prec))
         res_runs[name] = {
             "alone_latency_ms": {"p50": float(np.percentile(lat, 50)) * 1e-3,
                                  "p99": float(np.percentile(lat, 99)) * 1e-3,
-                                 "within_0p5ms": float((lat <= 500.0).mean())},
+                                 "within_0p5ms": float((lat <= 500.0).mean()),
+                                 "within_0p5ms_floor_below_0p25ms": float((lat[floor_ms < 0.25] <= 500.0).mean())},
             "service_model_us": {"fixed": est[0], "per_gflop": est[1]},
-            "capacity_jobs_per_s": cap, "capacity_fifo_unsplit_jobs_per_s": cap_fifo,
-            "at_offered_rate": offered,
-            "at_70pct_capacity": dict(sustained, rate_jobs_per_s=sus_rate),
-            "at_70pct_capacity_fifo_unsplit": sustained_fifo}
+            "capacity_jobs_per_s": caps,
+            "at_70pct_fifo_capacity": dict(at70, rate_jobs_per_s=sus_rate),
+            "at_offered_rate_fifo": offered}
     ctx.close()
-    main_run = res_runs["fp16"]["at_70pct_capacity"]
+    main_run = res_runs["fp16"]["at_70pct_fifo_capacity"]["fifo"]
     res = {
         "metric": METRIC, "value": main_run["vectors_per_s"], "unit": "vectors/s", "n_gpus": 1,
         "steps": None, "warmup": 50, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
@@ -832,12 +885,13 @@ def run_serving(args) -> int:
         "config": {"workload": SERVING_WORKLOAD, "offered_jobs_per_s": args.rate, "jobs_per_offered_run": args.jobs,
                    "pool_jobs": n_pool, "mean_vectors_per_job": float(np.mean([c.S * T for c in cells])),
                    "symbols": T, "snr_db": snr, "channel": "kron 0.5/0.3", "deadline_us": 500.0,
-                   "max_batch_jobs": 8, "max_inflight": 3, "max_queue": 256, "policy": "slack",
-                   "split_vectors": split, "hbm_budget_bytes": 16 << 30,
+                   "max_batch_jobs": 8, "max_inflight": 3, "max_queue": 256, "policy": "fifo",
+                   "split_vectors_of_split_variant": split, "hbm_budget_bytes": 16 << 30,
                    "floor": "path-search flops of the job at 157.3 TFLOP/s"},
         "p50_latency_ms": main_run["p50_latency_ms"], "p99_latency_ms": main_run["p99_latency_ms"],
         "runs": res_runs,
-        "mixed_vs_fp32_capacity": res_runs["fp16"]["capacity_jobs_per_s"] / res_runs["fp32"]["capacity_jobs_per_s"],
+        "mixed_vs_fp32_capacity": res_runs["fp16"]["capacity_jobs_per_s"]["fifo"] /
+        res_runs["fp32"]["capacity_jobs_per_s"]["fifo"],
     }
     print(json.dumps(res), flush=True)
     return 0

@@ -121,6 +121,18 @@ int mpnl_memory_usage(const mpnl_ctx *ctx, size_t *held, size_t *in_use);
 
 /* ---- measurement ------------------------------------------------------------ */
 
+/* Diagnostics for the roofline (not a detection call): time `waves`
+   one-wavefront workgroups that each run `iters` rounds of eight
+   independent VALU chains of one kind on `device` (0: v_fma_f32; 1: the
+   point-choice mix of the path search, round / clamp / subtract / square /
+   compare / select; 2: DPP row shifts), the second of two launches.
+   *ms_out receives the launch time.  Together with the counters of the same
+   launch (VALU wave-instructions) it gives the issue rate the compute units
+   reach for that mix.  Allocates and frees a small output buffer.  Errors:
+   MPNL_E_INVAL (kind outside 0..2, waves or iters < 1, null ms_out),
+   MPNL_E_HIP. */
+int mpnl_diag_valu_rate(int device, int kind, int waves, int iters, double *ms_out);
+
 /* Stages reported by the kernel timers. */
 #define MPNL_STAGE_SQRD 0        /* a1 sorted QR                               */
 #define MPNL_STAGE_POSVEC 1      /* a2 position-vector set                     */

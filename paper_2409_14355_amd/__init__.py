@@ -39,6 +39,7 @@ EXPORTED = (
     "mpnl_job_bytes", "mpnl_server_create", "mpnl_server_now_us", "mpnl_server_submit",
     "mpnl_server_poll", "mpnl_server_pending", "mpnl_server_run_poisson", "mpnl_server_destroy",
     "mpnl_sched_simulate", "mpnl_mmse_detect", "mpnl_detect_regularized", "mpnl_detect_static",
+    "mpnl_diag_valu_rate",
 )
 MPNL_JOB_DONE, MPNL_JOB_REJECTED, MPNL_JOB_DROPPED, MPNL_JOB_FAILED = 0, 1, 2, 3
 MPNL_CREATE_NO_PRUNE = 1
@@ -118,6 +119,7 @@ def lib() -> ctypes.CDLL:
     L.mpnl_batch_run.argtypes = [vp, vp, ctypes.POINTER(mpnl_job), vp]
     L.mpnl_batch_info.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), ip]
     L.mpnl_batch_destroy.argtypes = [vp, vp]
+    L.mpnl_diag_valu_rate.argtypes = [ip, ip, ip, ip, ctypes.POINTER(ctypes.c_double)]
     L.mpnl_mmse_detect.argtypes = [vp, vp, vp, ip, ip, ip, ip, ip, ctypes.c_float, vp, vp]
     L.mpnl_detect_regularized.argtypes = [vp, vp, vp, ip, ip, ip, ip, ip, ip, ctypes.c_float, vp, vp]
     cfgp = ctypes.POINTER(mpnl_server_config)
@@ -291,6 +293,13 @@ def mpnl_batch_info(batch: int, max_launches: int = 128) -> list[dict]:
     _check(lib().mpnl_batch_info(batch, ctypes.byref(n), v, max_launches), "mpnl_batch_info")
     keys = ("N", "mod", "lanes", "group_lanes", "items_per_workgroup", "group_major", "workgroups")
     return [dict(zip(keys, v[7 * i:7 * i + 7])) for i in range(min(n.value, max_launches))]
+
+
+def mpnl_diag_valu_rate(device: int, kind: int, waves: int, iters: int) -> float:
+    """-> milliseconds of the VALU issue probe launch (see mpnl.h)."""
+    ms = ctypes.c_double()
+    _check(lib().mpnl_diag_valu_rate(device, kind, waves, iters, ctypes.byref(ms)), "mpnl_diag_valu_rate")
+    return ms.value
 
 
 def mpnl_batch_destroy(ctx: int, batch: int) -> None:

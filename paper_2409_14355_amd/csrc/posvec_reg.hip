@@ -110,6 +110,7 @@ struct PosLds {
     uint32_t run[KP];    // exclusive prefix of cnt inside each wavefront
     uint32_t wsum[E];    // cnt total of each wavefront
     uint32_t ap0;        // packed word of entry 0 of A
+    uint32_t apK1;       // packed word of entry K - 1 of A
 };
 
 // LDS of one workgroup: PosLds, then N * KP back pointers per depth, 16 bits
@@ -143,15 +144,36 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
     sh.cnt[g] = 0;
     if (g == 0)
         sh.ap0 = 0u;
+    if (g == K - 1)
+        sh.apK1 = Ap;
+    // the weights of all depths, lane d holding w_d (N <= 32), read per
+    // depth from a register instead of a dependent load
+    const double wl = lane < N ? a.w[(size_t)s * N + lane] : 0.0;
     __syncthreads();
 
     int buf = 0;
     for (int d = 0; d < N; ++d) {
-        const double w = a.w[(size_t)s * N + d];
+        const double w = lane_read(wl, d);
         double Zs = As;
         uint32_t Zp = Ap;
         const double a0s = sh.scA[0];
         const uint32_t a0p = sh.ap0;
+        // A full list that not even the cheapest entry with rank 2 at this
+        // depth (entry 0 raised by one) can enter: every prefix extends by
+        // rank 1 only, so positions, scores and lexical ranks stay as they
+        // are and only the back pointers (parent = itself, k = 0) are
+        // written; no LDS state changes, no barrier.  (The merge loop below
+        // would stop at its first check and the rank pass reproduce the
+        // ranks.)  The decision reads LDS written before the last barrier,
+        // so every lane takes it alike.
+        if (d > 0) {
+            const double lastS = sh.scA[K - 1];
+            if (lastS < INF && !key_lt(cand_score_r(a0s, w, 1), (a0p & 0xfffc0fffu) | (1u << 12), lastS, sh.apK1)) {
+                if (As < INF)
+                    rec[(size_t)d * KP + g] = (uint16_t)(g & 0xff);
+                continue;
+            }
+        }
         // The first depth extends the root only: its children k = 0 .. |Q|-1
         // are already in key order (scores non-decreasing in k, equal scores
         // ordered by k), so entry g is child g and no merge is needed.
@@ -272,6 +294,8 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
         sh.scA[g] = As;
         if (g == 0)
             sh.ap0 = Ap;
+        if (g == K - 1)
+            sh.apK1 = Ap;
         __syncthreads();
     }
 

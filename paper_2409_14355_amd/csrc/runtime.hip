@@ -897,188 +897,6 @@ int mpnl_detect_static(mpnl_ctx *ctx, const void *H, const void *y, int S, int T
                        (hipStream_t)stream);
 }
 
-int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *stream)
-{
-    if (!ctx || !jobs || n_jobs <= 0)
-        return MPNL_E_INVAL;
-    for (int i = 0; i < n_jobs; ++i) {
-        const mpnl_job &j = jobs[i];
-        if (!j.H || !j.y || !j.out || j.T <= 0)
-            return MPNL_E_INVAL;
-        int rc = validate_shape(j.S, j.M, j.N, j.mod, j.n_paths);
-        if (rc != MPNL_OK)
-            return rc;
-        if ((long long)j.S * j.T > INT_MAX / 4)
-            return MPNL_E_UNSUPPORTED;
-    }
-    DeviceGuard g(ctx->device);
-    if (!g.ok())
-        return hip_fail(ctx, hipErrorInvalidDevice);
-    hipStream_t st = (hipStream_t)stream;
-
-    // a1-a3 per job; a job with more than 256 paths also runs its own a4+a5
-    std::vector<mpnl_slot *> slots(n_jobs, nullptr);
-    std::vector<int> ytb(n_jobs, -1);
-    std::vector<char> batched(n_jobs, 0);
-    int rc = MPNL_OK;
-    for (int i = 0; i < n_jobs && rc == MPNL_OK; ++i) {
-        const mpnl_job &j = jobs[i];
-        rc = prepare_impl(ctx, j.H, j.S, j.M, j.N, j.mod, j.n_paths, st, &slots[i]);
-        if (rc != MPNL_OK)
-            break;
-        if (slots[i]->sd.K > 256) {
-            rc = detect_impl(ctx, slots[i], j.y, j.T, j.out, st, false, 0.f, 0.f, nullptr);
-            continue;
-        }
-        batched[i] = 1;
-        rc = pool_alloc(ctx, align_up((size_t)j.T * j.S * j.N * sizeof(float2)) +
-                                 (ctx->prune ? align_up(mpnl::bound_record_bytes(j.S, j.T, j.N)) : 0) +
-                                 mpnl::multi_partial_bytes(j.S, j.T, j.N, slots[i]->sd.K),
-                        st, &ytb[i]);
-        if (rc != MPNL_OK)
-            break;
-        hipError_t e;
-        {
-            StageTimer tm(ctx, MPNL_STAGE_ROTATE, st);
-            e = mpnl::launch_rotate(slots[i]->sd, (const float2 *)j.y, j.T,
-                                    (float2 *)ctx->blocks[ytb[i]].ptr, st);
-        }
-        if (e != hipSuccess)
-            rc = hip_fail(ctx, e);
-    }
-
-    // a4+a5: one launch per (user count, modulation, workgroup size = paths
-    // rounded up to a wavefront)
-    if (rc == MPNL_OK) {
-        struct Group {
-            int N, bits, threads;
-            std::vector<int> idx;
-        };
-        std::vector<Group> groups;
-        for (int i = 0; i < n_jobs; ++i) {
-            if (!batched[i])
-                continue;
-            const int N = jobs[i].N, bits = jobs[i].mod;
-            const int thr = (slots[i]->sd.K + 63) / 64 * 64;
-            auto it = std::find_if(groups.begin(), groups.end(), [&](const Group &q) {
-                return q.N == N && q.bits == bits && q.threads == thr;
-            });
-            if (it == groups.end()) {
-                groups.push_back({N, bits, thr, {}});
-                it = groups.end() - 1;
-            }
-            it->idx.push_back(i);
-        }
-        // job tables of every group in one upload
-        size_t table_bytes = 0;
-        std::vector<size_t> goff(groups.size());
-        for (size_t q = 0; q < groups.size(); ++q) {
-            goff[q] = table_bytes;
-            table_bytes += align_up(groups[q].idx.size() * sizeof(mpnl::JobDev));
-        }
-        // staging buffer: the first idle one of the ring, else wait for the oldest
-        mpnl_ctx::Staging *sg = nullptr;
-        for (int k = 0; k < 4 && !sg; ++k) {
-            mpnl_ctx::Staging &c = ctx->staging[(ctx->staging_next + k) % 4];
-            if (!c.pending || hipEventQuery(c.ev) == hipSuccess)
-                sg = &c;
-        }
-        if (!sg) {
-            sg = &ctx->staging[ctx->staging_next];
-            if (hipEventSynchronize(sg->ev) != hipSuccess)
-                rc = MPNL_E_HIP;
-        }
-        ctx->staging_next = (int)(sg - ctx->staging + 1) % 4;
-        if (rc == MPNL_OK && sg->size < table_bytes) {
-            if (sg->ptr)
-                (void)hipHostFree(sg->ptr);
-            sg->ptr = nullptr;
-            sg->size = 0;
-            hipError_t e = hipHostMalloc(&sg->ptr, table_bytes, hipHostMallocDefault);
-            if (e != hipSuccess)
-                rc = hip_fail(ctx, e);
-            else
-                sg->size = table_bytes;
-        }
-        if (rc == MPNL_OK && !sg->ev) {
-            hipError_t e = hipEventCreateWithFlags(&sg->ev, hipEventDisableTiming);
-            if (e != hipSuccess)
-                rc = hip_fail(ctx, e);
-        }
-        int tblk = -1;
-        if (rc == MPNL_OK && !groups.empty())
-            rc = pool_alloc(ctx, table_bytes, st, &tblk);
-        if (rc == MPNL_OK && !groups.empty()) {
-            char *host = (char *)sg->ptr;
-            char *dev = (char *)ctx->blocks[tblk].ptr;
-            std::vector<int> items(groups.size()), threads(groups.size()), bitems(groups.size());
-            for (size_t q = 0; q < groups.size(); ++q) {
-                mpnl::JobDev *jd = (mpnl::JobDev *)(host + goff[q]);
-                int acc = 0, bacc = 0;
-                for (size_t u = 0; u < groups[q].idx.size(); ++u) {
-                    const int i = groups[q].idx[u];
-                    const mpnl::SlotDev &sd = slots[i]->sd;
-                    mpnl::JobDev &J = jd[u];
-                    char *wb = (char *)ctx->blocks[ytb[i]].ptr;
-                    const size_t yt_bytes = align_up((size_t)jobs[i].T * sd.S * sd.N * sizeof(float2));
-                    const size_t bd_bytes =
-                        ctx->prune ? align_up(mpnl::bound_record_bytes(sd.S, jobs[i].T, sd.N)) : 0;
-                    J.yt = (const float2 *)wb;
-                    J.bound = ctx->prune ? (float *)(wb + yt_bytes) : nullptr;
-                    J.part = mpnl::multi_partial_bytes(sd.S, jobs[i].T, sd.N, sd.K) ? (float *)(wb + yt_bytes + bd_bytes)
-                                                                                     : nullptr;
-                    J.bound_begin = bacc;
-                    bacc += (sd.S * jobs[i].T + 63) / 64;
-                    J.rlat = sd.rlat;
-                    J.rq = rq_of(sd, ctx->precision);
-                    J.diag = sd.diag;
-                    J.permd = sd.permd;
-                    J.P = sd.P;
-                    J.order = sd.order;
-                    J.out = jobs[i].out;
-                    J.S = sd.S;
-                    J.T = jobs[i].T;
-                    J.N = sd.N;
-                    J.K = sd.K;
-                    J.NP = sd.NP;
-                    J.item_begin = acc;
-                    acc += sd.S * jobs[i].T;
-                }
-                items[q] = acc;
-                bitems[q] = bacc;
-                threads[q] = groups[q].threads;
-            }
-            hipError_t e = hipMemcpyAsync(dev, host, table_bytes, hipMemcpyHostToDevice, st);
-            if (e == hipSuccess)
-                e = hipEventRecord(sg->ev, st);
-            sg->pending = e == hipSuccess;
-            for (size_t q = 0; q < groups.size() && e == hipSuccess; ++q) {
-                const mpnl::JobDev *jd = (const mpnl::JobDev *)(dev + goff[q]);
-                if (ctx->prune) {
-                    StageTimer tb(ctx, MPNL_STAGE_BOUND, st);
-                    e = mpnl::launch_path_bound_multi(jd, (int)groups[q].idx.size(), bitems[q], groups[q].N,
-                                                      groups[q].bits, ctx->precision, st);
-                }
-                StageTimer tm(ctx, MPNL_STAGE_PATHS, st);
-                if (e == hipSuccess)  // one-wavefront path groups, group major, four per workgroup
-                    e = mpnl::launch_path_search_multi(jd, (int)groups[q].idx.size(), items[q], groups[q].N,
-                                                       groups[q].bits, ctx->precision, threads[q],
-                                                       threads[q] / 64, 4, 1, st);
-            }
-            if (e != hipSuccess)
-                rc = hip_fail(ctx, e);
-            pool_release(ctx, tblk, st);
-        }
-    }
-    for (int i = 0; i < n_jobs; ++i) {
-        if (ytb[i] >= 0)
-            pool_release(ctx, ytb[i], st);
-        if (slots[i])
-            release_impl(ctx, slots[i]);
-    }
-    return rc;
-}
-
 int mpnl_detect_regularized(mpnl_ctx *ctx, const void *H, const void *y, int S, int T, int M, int N, int mod,
                             int n_paths, float sigma2, int32_t *out, void *stream)
 {
@@ -1169,6 +987,12 @@ struct PlanLaunch {
 
 constexpr int kGraphCopies = 2;
 
+// Byte offsets of one job's arrays in a batch's block.
+struct PlanJobOffsets {
+    SlotLayout lay;
+    size_t base, yt, bound, part;
+};
+
 }  // namespace
 
 struct mpnl_batch {
@@ -1177,6 +1001,7 @@ struct mpnl_batch {
     std::vector<float2 *> yt;
     std::vector<float *> bound;  // per job pruning bounds, or null
     std::vector<float *> part;   // per job path-group partial records, or null (one group)
+    std::vector<PlanJobOffsets> off;
     std::vector<PlanLaunch> launches;
     int block = -1;
     size_t table_bytes = 0;
@@ -1195,6 +1020,118 @@ struct mpnl_batch {
 };
 
 namespace {
+
+// Device-memory layout and launch groups of a batch of job shapes (every
+// job with n_paths clamped to <= 256): per job its slot state, rotated
+// vectors, pruning record and path-group partials, then the job tables.
+// Fills p->launches, p->table_bytes and the per-job offsets; returns the
+// bytes before the tables (each table copy takes p->table_bytes more).
+size_t plan_layout(mpnl_batch *p, bool prune)
+{
+    const int n_jobs = (int)p->shapes.size();
+    p->off.assign(n_jobs, PlanJobOffsets{});
+    size_t total = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        const mpnl_job &j = p->shapes[i];
+        const int K = (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
+        PlanJobOffsets &o = p->off[i];
+        o.lay = slot_layout(j.S, j.M, j.N, K, (j.N + 3) / 4 * 4, false);
+        o.base = total;
+        total += o.lay.total;
+        o.yt = total;
+        total += align_up((size_t)j.T * j.S * j.N * sizeof(float2));
+        o.bound = total;
+        if (prune)
+            total += align_up(mpnl::bound_record_bytes(j.S, j.T, j.N));
+        o.part = total;
+        total += align_up(mpnl::multi_partial_bytes(j.S, j.T, j.N, K));
+    }
+    // launch groups
+    p->launches.clear();
+    auto group = [&](int kind, int param, int bits, int threads) -> PlanLaunch & {
+        for (PlanLaunch &L : p->launches)
+            if (L.kind == kind && L.param == param && L.bits == bits && L.threads == threads)
+                return L;
+        PlanLaunch L{};
+        L.kind = kind;
+        L.param = param;
+        L.bits = bits;
+        L.threads = threads;
+        L.groups = kind == L_PATHS ? threads / 64 : 1;  // one-wavefront path groups, group major,
+        L.vpw = kind == L_PATHS ? 4 : 1;                 // four a workgroup, unless tuned
+        L.gmajor = 1;
+        p->launches.push_back(L);
+        return p->launches.back();
+    };
+    for (int stage = 0; stage < 4; ++stage)
+        for (int i = 0; i < n_jobs; ++i) {
+            const mpnl_job &j = p->shapes[i];
+            const int K = (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
+            PlanLaunch *L;
+            if (stage == L_SQRD) {
+                L = &group(L_SQRD, (j.M + 3) / 4 * 4, 0, 64);
+                L->items += (j.S + 1) / 2;
+            } else if (stage == L_POSVEC) {
+                L = &group(L_POSVEC, K <= 64 ? 1 : K <= 128 ? 2 : 4, 0, 64);
+                L->items += j.S;
+                L->nmax = std::max(L->nmax, j.N);
+            } else if (stage == L_ROTATE) {
+                L = &group(L_ROTATE, 0, 0, 64);
+                L->items += j.S;
+            } else {
+                L = &group(L_PATHS, j.N, j.mod, (K + 63) / 64 * 64);
+                L->items += j.S * j.T;
+                L->bound_items += (j.S * j.T + 63) / 64;
+            }
+            L->jobs.push_back(i);
+        }
+    p->table_bytes = 0;
+    for (PlanLaunch &L : p->launches) {
+        L.off = p->table_bytes;
+        const size_t entry = L.kind == L_PATHS ? sizeof(mpnl::JobDev) : sizeof(mpnl::dev::StageJob);
+        p->table_bytes += align_up(L.jobs.size() * entry);
+    }
+    return total;
+}
+
+// Point every job's slot state and workspace into the block at dbase (laid
+// out by plan_layout).
+void plan_bind(mpnl_batch *p, char *dbase)
+{
+    p->sd.clear();
+    p->yt.clear();
+    p->bound.clear();
+    p->part.clear();
+    for (size_t i = 0; i < p->shapes.size(); ++i) {
+        const mpnl_job &j = p->shapes[i];
+        const PlanJobOffsets &o = p->off[i];
+        const SlotLayout &L = o.lay;
+        char *b = dbase + o.base;
+        mpnl::SlotDev sd{};
+        sd.S = j.S;
+        sd.M = j.M;
+        sd.N = j.N;
+        sd.bits = j.mod;
+        sd.K = (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
+        sd.NP = (j.N + 3) / 4 * 4;
+        sd.Qd = (float2 *)(b + L.Qd);
+        sd.roff = (float2 *)(b + L.roff);
+        sd.rlat = (float2 *)(b + L.rlat);
+        sd.rlat_h = (uint32_t *)(b + L.rlat_h);
+        sd.rlat_b = (uint32_t *)(b + L.rlat_b);
+        sd.diag = (float4 *)(b + L.diag);
+        sd.wd = (double *)(b + L.wd);
+        sd.permd = (int32_t *)(b + L.permd);
+        sd.P = (uint8_t *)(b + L.P);
+        sd.order = (uint16_t *)(b + L.order);
+        sd.rec = nullptr;
+        sd.rec16 = nullptr;
+        p->sd.push_back(sd);
+        p->yt.push_back((float2 *)(dbase + o.yt));
+        p->bound.push_back(p->prune ? (float *)(dbase + o.bound) : nullptr);
+        p->part.push_back(mpnl::multi_partial_bytes(j.S, j.T, j.N, sd.K) ? (float *)(dbase + o.part) : nullptr);
+    }
+}
 
 // Fill table copy b for the given job pointers (pointers of the shapes are
 // ignored).
@@ -1253,33 +1190,40 @@ void plan_fill(mpnl_batch *p, int b, const mpnl_job *jobs)
 hipError_t plan_enqueue(mpnl_batch *p, int b, hipStream_t st, mpnl_ctx *timed = nullptr)
 {
     hipError_t e = hipMemcpyAsync(p->dev_table[b], p->pinned[b], p->table_bytes, hipMemcpyHostToDevice, st);
-    static const int stage_of[] = {MPNL_STAGE_SQRD, MPNL_STAGE_POSVEC, MPNL_STAGE_ROTATE, MPNL_STAGE_PATHS};
     for (const PlanLaunch &L : p->launches) {
         if (e != hipSuccess)
             break;
         char *tab = p->dev_table[b] + L.off;
         const int nj = (int)L.jobs.size();
         mpnl_ctx off{};
-        StageTimer tm(timed ? timed : &off, stage_of[L.kind], st);
+        mpnl_ctx *tc = timed ? timed : &off;
         switch (L.kind) {
-        case L_SQRD:
+        case L_SQRD: {
+            StageTimer tm(tc, MPNL_STAGE_SQRD, st);
             e = mpnl::launch_sqrd_batch((const mpnl::dev::StageJob *)tab, nj, L.items, L.param, st);
             break;
-        case L_POSVEC:
+        }
+        case L_POSVEC: {
+            StageTimer tm(tc, MPNL_STAGE_POSVEC, st);
             e = mpnl::launch_posvec_batch((const mpnl::dev::StageJob *)tab, nj, L.items, L.param, L.nmax, st);
             break;
-        case L_ROTATE:
+        }
+        case L_ROTATE: {
+            StageTimer tm(tc, MPNL_STAGE_ROTATE, st);
             e = mpnl::launch_rotate_batch((const mpnl::dev::StageJob *)tab, nj, L.items, st);
             break;
+        }
         default:
             if (p->prune) {
-                StageTimer tb(timed ? timed : &off, MPNL_STAGE_BOUND, st);
+                StageTimer tb(tc, MPNL_STAGE_BOUND, st);
                 e = mpnl::launch_path_bound_multi((const mpnl::JobDev *)tab, nj, L.bound_items, L.param, L.bits,
                                                   p->precision, st);
             }
-            if (e == hipSuccess)
+            if (e == hipSuccess) {  // the path search and its group reduction
+                StageTimer tm(tc, MPNL_STAGE_PATHS, st);
                 e = mpnl::launch_path_search_multi((const mpnl::JobDev *)tab, nj, L.items, L.param, L.bits,
                                                    p->precision, L.threads, L.groups, L.vpw, L.gmajor, st);
+            }
         }
     }
     return e;
@@ -1396,6 +1340,102 @@ void plan_free(mpnl_ctx *ctx, mpnl_batch *p)
 
 extern "C" {
 
+int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *stream)
+{
+    if (!ctx || !jobs || n_jobs <= 0)
+        return MPNL_E_INVAL;
+    for (int i = 0; i < n_jobs; ++i) {
+        const mpnl_job &j = jobs[i];
+        if (!j.H || !j.y || !j.out || j.T <= 0)
+            return MPNL_E_INVAL;
+        int rc = validate_shape(j.S, j.M, j.N, j.mod, j.n_paths);
+        if (rc != MPNL_OK)
+            return rc;
+        if ((long long)j.S * j.T > INT_MAX / 4)
+            return MPNL_E_UNSUPPORTED;
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok())
+        return hip_fail(ctx, hipErrorInvalidDevice);
+    hipStream_t st = (hipStream_t)stream;
+
+    // a job with more than 256 paths runs a1..a5 on its own; the others as
+    // one batch: a1, a2 and a3 of all of them in one launch per bucket, then
+    // one path-search launch per (user count, modulation, paths rounded up
+    // to a wavefront), the same launches a planned batch replays
+    std::vector<mpnl_job> small;
+    int rc = MPNL_OK;
+    for (int i = 0; i < n_jobs && rc == MPNL_OK; ++i) {
+        const mpnl_job &j = jobs[i];
+        if (std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N)) <= 256) {
+            small.push_back(j);
+            continue;
+        }
+        mpnl_slot *slot = nullptr;
+        rc = prepare_impl(ctx, j.H, j.S, j.M, j.N, j.mod, j.n_paths, st, &slot);
+        if (rc != MPNL_OK)
+            break;
+        rc = detect_impl(ctx, slot, j.y, j.T, j.out, st, false, 0.f, 0.f, nullptr);
+        release_impl(ctx, slot);
+    }
+    if (rc != MPNL_OK || small.empty())
+        return rc;
+
+    mpnl_batch p;
+    p.shapes = small;
+    p.precision = ctx->precision;
+    p.prune = ctx->prune;
+    const size_t tables_at = plan_layout(&p, ctx->prune);
+    // pinned staging buffer of the job tables: the first idle one of the
+    // ring, else wait for the oldest
+    mpnl_ctx::Staging *sg = nullptr;
+    for (int k = 0; k < 4 && !sg; ++k) {
+        mpnl_ctx::Staging &c = ctx->staging[(ctx->staging_next + k) % 4];
+        if (!c.pending || hipEventQuery(c.ev) == hipSuccess)
+            sg = &c;
+    }
+    if (!sg) {
+        sg = &ctx->staging[ctx->staging_next];
+        if (hipEventSynchronize(sg->ev) != hipSuccess)
+            return MPNL_E_HIP;
+    }
+    ctx->staging_next = (int)(sg - ctx->staging + 1) % 4;
+    if (sg->size < p.table_bytes) {
+        if (sg->ptr)
+            (void)hipHostFree(sg->ptr);
+        sg->ptr = nullptr;
+        sg->size = 0;
+        hipError_t e = hipHostMalloc(&sg->ptr, p.table_bytes, hipHostMallocDefault);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e);
+        sg->size = p.table_bytes;
+    }
+    if (!sg->ev) {
+        hipError_t e = hipEventCreateWithFlags(&sg->ev, hipEventDisableTiming);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e);
+    }
+    int blk = -1;
+    rc = pool_alloc(ctx, tables_at + p.table_bytes, st, &blk);
+    if (rc != MPNL_OK)
+        return rc;
+    char *base = (char *)ctx->blocks[blk].ptr;
+    plan_bind(&p, base);
+    p.pinned[0] = sg->ptr;
+    p.dev_table[0] = base + tables_at;
+    plan_fill(&p, 0, small.data());
+    hipError_t e = plan_enqueue(&p, 0, st, ctx->prof ? ctx : nullptr);
+    if (e == hipSuccess)
+        e = hipEventRecord(sg->ev, st);  // the table upload (first in the stream) has read the buffer
+    sg->pending = e == hipSuccess;
+    pool_release(ctx, blk, st);
+    p.pinned[0] = nullptr;
+    if (e != hipSuccess)
+        return hip_fail(ctx, e);
+    return MPNL_OK;
+}
+
+
 int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigned flags, mpnl_batch **out)
 {
     if (!ctx || !shapes || n_jobs <= 0 || !out || (flags & ~MPNL_BATCH_AUTOTUNE))
@@ -1424,106 +1464,15 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
     p->precision = ctx->precision;
     p->prune = ctx->prune;
 
-    // device memory: every job's slot state and rotated vectors
-    std::vector<SlotLayout> lay(n_jobs);
-    std::vector<size_t> base(n_jobs), ytoff(n_jobs), boff(n_jobs), poff(n_jobs);
-    size_t total = 0;
-    for (int i = 0; i < n_jobs; ++i) {
-        const mpnl_job &j = shapes[i];
-        const int K = (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
-        lay[i] = slot_layout(j.S, j.M, j.N, K, (j.N + 3) / 4 * 4, false);
-        base[i] = total;
-        total += lay[i].total;
-        ytoff[i] = total;
-        total += align_up((size_t)j.T * j.S * j.N * sizeof(float2));
-        boff[i] = total;
-        if (ctx->prune)
-            total += align_up(mpnl::bound_record_bytes(j.S, j.T, j.N));
-        poff[i] = total;
-        total += align_up(mpnl::multi_partial_bytes(j.S, j.T, j.N, K));
-    }
-    // launch groups
-    auto group = [&](int kind, int param, int bits, int threads) -> PlanLaunch & {
-        for (PlanLaunch &L : p->launches)
-            if (L.kind == kind && L.param == param && L.bits == bits && L.threads == threads)
-                return L;
-        PlanLaunch L{};
-        L.kind = kind;
-        L.param = param;
-        L.bits = bits;
-        L.threads = threads;
-        L.groups = kind == L_PATHS ? threads / 64 : 1;  // one-wavefront path groups, group major,
-        L.vpw = kind == L_PATHS ? 4 : 1;                 // four a workgroup, unless tuned
-        L.gmajor = 1;
-        p->launches.push_back(L);
-        return p->launches.back();
-    };
-    for (int stage = 0; stage < 4; ++stage)
-        for (int i = 0; i < n_jobs; ++i) {
-            const mpnl_job &j = shapes[i];
-            const int K = (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
-            PlanLaunch *L;
-            if (stage == L_SQRD) {
-                L = &group(L_SQRD, (j.M + 3) / 4 * 4, 0, 64);
-                L->items += (j.S + 1) / 2;
-            } else if (stage == L_POSVEC) {
-                L = &group(L_POSVEC, K <= 64 ? 1 : K <= 128 ? 2 : 4, 0, 64);
-                L->items += j.S;
-                L->nmax = std::max(L->nmax, j.N);
-            } else if (stage == L_ROTATE) {
-                L = &group(L_ROTATE, 0, 0, 64);
-                L->items += j.S;
-            } else {
-                L = &group(L_PATHS, j.N, j.mod, (K + 63) / 64 * 64);
-                L->items += j.S * j.T;
-                L->bound_items += (j.S * j.T + 63) / 64;
-            }
-            L->jobs.push_back(i);
-        }
-    p->table_bytes = 0;
-    for (PlanLaunch &L : p->launches) {
-        L.off = p->table_bytes;
-        const size_t entry = L.kind == L_PATHS ? sizeof(mpnl::JobDev) : sizeof(mpnl::dev::StageJob);
-        p->table_bytes += align_up(L.jobs.size() * entry);
-    }
-    ytoff.push_back(0);
-    const size_t tables_at = total;
-    total += kGraphCopies * p->table_bytes;
-
+    const size_t tables_at = plan_layout(p, ctx->prune);
+    const size_t total = tables_at + kGraphCopies * p->table_bytes;
     int rc = pool_alloc(ctx, total, nullptr, &p->block);
     if (rc != MPNL_OK) {
         delete p;
         return rc;
     }
     char *dbase = (char *)ctx->blocks[p->block].ptr;
-    for (int i = 0; i < n_jobs; ++i) {
-        const mpnl_job &j = shapes[i];
-        const SlotLayout &L = lay[i];
-        char *b = dbase + base[i];
-        mpnl::SlotDev sd{};
-        sd.S = j.S;
-        sd.M = j.M;
-        sd.N = j.N;
-        sd.bits = j.mod;
-        sd.K = (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
-        sd.NP = (j.N + 3) / 4 * 4;
-        sd.Qd = (float2 *)(b + L.Qd);
-        sd.roff = (float2 *)(b + L.roff);
-        sd.rlat = (float2 *)(b + L.rlat);
-        sd.rlat_h = (uint32_t *)(b + L.rlat_h);
-        sd.rlat_b = (uint32_t *)(b + L.rlat_b);
-        sd.diag = (float4 *)(b + L.diag);
-        sd.wd = (double *)(b + L.wd);
-        sd.permd = (int32_t *)(b + L.permd);
-        sd.P = (uint8_t *)(b + L.P);
-        sd.order = (uint16_t *)(b + L.order);
-        sd.rec = nullptr;
-        sd.rec16 = nullptr;
-        p->sd.push_back(sd);
-        p->yt.push_back((float2 *)(dbase + ytoff[i]));
-        p->bound.push_back(ctx->prune ? (float *)(dbase + boff[i]) : nullptr);
-        p->part.push_back(mpnl::multi_partial_bytes(j.S, j.T, j.N, sd.K) ? (float *)(dbase + poff[i]) : nullptr);
-    }
+    plan_bind(p, dbase);
     hipError_t e = hipSuccess;
     for (int b = 0; b < kGraphCopies && e == hipSuccess; ++b) {
         p->dev_table[b] = dbase + tables_at + b * p->table_bytes;
