@@ -687,16 +687,17 @@ __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cp
     }
 }
 
-// Occupancy of the path searches: eight wavefronts per SIMD (64 VGPRs).  The
-// descent is bound by the latency of its per-depth scalar loads of R and y
-// more than by VALU issue, so more resident wavefronts pay even where the
-// decided symbols of the deeper depths spill to scratch (16 users: 0.128 ->
-// 0.116 ms per 1200 x 14 launch; 24 users: 0.477 -> 0.352 ms per 3276 x 14).
-// The multi-job kernel carries more state: there only FP32 fits 64 VGPRs
-// well; FP16 / BF16 run six wavefronts (80 VGPRs): 40 cells in FP16 take
-// 9.93 ms at their natural four to five, 9.84 at six, 11.7 at eight.
+// Occupancy of the path searches.  The descent is bound by the latency of
+// its per-depth scalar loads of R and y as much as by VALU issue, so more
+// resident wavefronts pay even where the decided symbols of the deeper depths
+// spill to scratch: in FP32 eight wavefronts per SIMD (64 VGPRs; 16 users:
+// 0.128 -> 0.116 ms per 1200 x 14 launch, 24 users: 0.477 -> 0.352 ms per
+// 3276 x 14, before the one-wavefront path groups).  FP16 / BF16 keep more
+// state per lane (packed operands and conversions) and run six (80 VGPRs):
+// the 40-cell FP16 batch takes 4.47 ms of path search at six against 5.76 ms
+// at eight; the one-job 24-user slot 0.250 against 0.262 ms (16 users: equal).
 template <int PREC>
-struct MultiOccupancy {
+struct PathOccupancy {
     static constexpr int waves = PREC == PREC_FP32 ? 8 : 6;
 };
 
@@ -726,7 +727,8 @@ __device__ __forceinline__ void work_item(int b, int nblocks, int q, int nvec, i
 // vectors numbered subcarrier-major (s T + t).
 // partials: (S * T, groups, 2 + (N + 3) / 4)
 template <int N, int L, int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void path_search_kernel(PathArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PathOccupancy<PREC>::waves))) void
+path_search_kernel(PathArgs a)
 {
     __shared__ float sm[4];
     __shared__ int sr[4];
@@ -914,7 +916,7 @@ struct MultiArgs {
 };
 
 template <int N, int L, int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MultiOccupancy<PREC>::waves))) void
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PathOccupancy<PREC>::waves))) void
 path_search_multi_kernel(MultiArgs a)
 {
     __shared__ float sm[4];
