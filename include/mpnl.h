@@ -139,7 +139,13 @@ int mpnl_diag_valu_rate(int device, int kind, int waves, int iters, double *ms_o
 #define MPNL_STAGE_ROTATE 2      /* a3 yt = Q^H y                              */
 #define MPNL_STAGE_PATHS 3       /* a4 + a5 path search and minimum            */
 #define MPNL_STAGE_BOUND 4       /* path 0's metric per vector (pruning bound) */
-#define MPNL_NUM_STAGES 5
+#define MPNL_STAGE_PATH_WINDOW 5 /* planned batch only: from its first bound or
+                                    path launch to the end of its last one, on
+                                    the batch's stream; the launches may run
+                                    side by side on graph branches, so this
+                                    wall time can be below the PATHS + BOUND
+                                    sums, which count each launch in full     */
+#define MPNL_NUM_STAGES 6
 
 /* Enable (1) or disable (0) kernel timers: while enabled every kernel launch
    of the context is bracketed by two HIP events recorded on its stream.

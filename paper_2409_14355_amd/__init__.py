@@ -45,7 +45,8 @@ MPNL_JOB_DONE, MPNL_JOB_REJECTED, MPNL_JOB_DROPPED, MPNL_JOB_FAILED = 0, 1, 2, 3
 MPNL_CREATE_NO_PRUNE = 1
 MPNL_BATCH_AUTOTUNE = 1
 MPNL_STAGE_SQRD, MPNL_STAGE_POSVEC, MPNL_STAGE_ROTATE, MPNL_STAGE_PATHS, MPNL_STAGE_BOUND = 0, 1, 2, 3, 4
-STAGE_NAMES = ("sqrd", "posvec", "rotate", "paths", "bound")
+MPNL_STAGE_PATH_WINDOW = 5
+STAGE_NAMES = ("sqrd", "posvec", "rotate", "paths", "bound", "path_window")
 
 
 class mpnl_server_config(ctypes.Structure):

@@ -979,6 +979,8 @@ struct PlanLaunch {
     int groups;       // a4: path groups per vector (threads / 64, or 1: the whole vector) (tuned)
     int vpw;          // a4: work items (vector, path group) per workgroup (tuned)
     int gmajor;       // a4: 1 = work items numbered path group major (tuned)
+    int branch;       // a4: graph branch of the launch (plan_branches)
+    double gflop;     // a4: path-search work of the launch (algorithmic)
     int bound_items;  // a4: items of the pruning-bound launch
     int items;
     size_t off;       // byte offset of the job table in a table buffer
@@ -986,6 +988,9 @@ struct PlanLaunch {
 };
 
 constexpr int kGraphCopies = 2;
+// branches of the planned batch's path-search launches
+constexpr int kMaxBranches = 4;
+constexpr int kPlanBranches = 3;
 
 // Byte offsets of one job's arrays in a batch's block.
 struct PlanJobOffsets {
@@ -1017,6 +1022,13 @@ struct mpnl_batch {
     int precision = MPNL_PREC_FP32;
     bool prune = true;
     hipStream_t cap = nullptr;
+    // path-search launches split over kPlanBranches branches of the graph
+    // (see plan_enqueue): the other branches' streams, the fork event and
+    // their join events
+    int branches = 1;
+    hipStream_t side[kMaxBranches - 1] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kMaxBranches - 1] = {};
 };
 
 namespace {
@@ -1082,6 +1094,7 @@ size_t plan_layout(mpnl_batch *p, bool prune)
                 L = &group(L_PATHS, j.N, j.mod, (K + 63) / 64 * 64);
                 L->items += j.S * j.T;
                 L->bound_items += (j.S * j.T + 63) / 64;
+                L->gflop += (double)j.S * j.T * K * (4.0 * j.N * (j.N - 1) + 11.0 * j.N) * 1e-9;
             }
             L->jobs.push_back(i);
         }
@@ -1130,6 +1143,24 @@ void plan_bind(mpnl_batch *p, char *dbase)
         p->yt.push_back((float2 *)(dbase + o.yt));
         p->bound.push_back(p->prune ? (float *)(dbase + o.bound) : nullptr);
         p->part.push_back(mpnl::multi_partial_bytes(j.S, j.T, j.N, sd.K) ? (float *)(dbase + o.part) : nullptr);
+    }
+}
+
+// Spread the path-search launches over `branches` graph branches: largest
+// algorithmic work first, each to the branch with the least work so far.
+void plan_branches(mpnl_batch *p, int branches)
+{
+    std::vector<PlanLaunch *> paths;
+    for (PlanLaunch &L : p->launches)
+        if (L.kind == L_PATHS)
+            paths.push_back(&L);
+    std::stable_sort(paths.begin(), paths.end(),
+                     [](const PlanLaunch *a, const PlanLaunch *b) { return a->gflop > b->gflop; });
+    std::vector<double> load(std::max(branches, 1), 0.0);
+    for (PlanLaunch *L : paths) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        L->branch = b;
+        load[b] += L->gflop;
     }
 }
 
@@ -1190,9 +1221,43 @@ void plan_fill(mpnl_batch *p, int b, const mpnl_job *jobs)
 hipError_t plan_enqueue(mpnl_batch *p, int b, hipStream_t st, mpnl_ctx *timed = nullptr)
 {
     hipError_t e = hipMemcpyAsync(p->dev_table[b], p->pinned[b], p->table_bytes, hipMemcpyHostToDevice, st);
+    // With several branches the path-search launches (bound, search and
+    // reduction of one group stay together) go round-robin over `st` and
+    // the side streams after the rotation; the side streams join `st` again
+    // at the end: branches of the captured graph, so that the tail of one
+    // launch overlaps the next launches instead of leaving the device idle.
+    const bool fork = p->branches > 1;
+    bool forked = false, in_paths = false;
+    const hipStream_t st0 = st;
+    // the window of the path stage on `st`: first path launch to the join
+    hipEvent_t win0 = nullptr, win1 = nullptr;
+    if (timed && timed->prof) {
+        win0 = take_event(timed);
+        win1 = take_event(timed);
+    }
     for (const PlanLaunch &L : p->launches) {
         if (e != hipSuccess)
             break;
+        st = st0;
+        if (L.kind == L_PATHS && !in_paths) {
+            in_paths = true;
+            if (win0 && win1)
+                e = hipEventRecord(win0, st0);
+            if (e != hipSuccess)
+                break;
+        }
+        if (fork && L.kind == L_PATHS) {
+            if (!forked) {
+                e = hipEventRecord(p->fork_ev, st0);
+                for (int k = 0; k + 1 < p->branches && e == hipSuccess; ++k)
+                    e = hipStreamWaitEvent(p->side[k], p->fork_ev, 0);
+                if (e != hipSuccess)
+                    break;
+                forked = true;
+            }
+            const int br = L.branch % p->branches;
+            st = br ? p->side[br - 1] : st0;
+        }
         char *tab = p->dev_table[b] + L.off;
         const int nj = (int)L.jobs.size();
         mpnl_ctx off{};
@@ -1226,6 +1291,19 @@ hipError_t plan_enqueue(mpnl_batch *p, int b, hipStream_t st, mpnl_ctx *timed = 
             }
         }
     }
+    for (int k = 0; forked && k + 1 < p->branches && e == hipSuccess; ++k) {
+        e = hipEventRecord(p->join_ev[k], p->side[k]);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(st0, p->join_ev[k], 0);
+    }
+    if (in_paths && win0 && win1 && e == hipSuccess)
+        e = hipEventRecord(win1, st0);
+    if (in_paths && win0 && win1 && e == hipSuccess)
+        timed->timed.push_back({MPNL_STAGE_PATH_WINDOW, win0, win1});
+    else if (timed)
+        for (hipEvent_t x : {win0, win1})
+            if (x)
+                timed->spare_events.push_back(x);
     return e;
 }
 
@@ -1331,6 +1409,14 @@ void plan_free(mpnl_ctx *ctx, mpnl_batch *p)
     }
     if (p->cap)
         (void)hipStreamDestroy(p->cap);
+    for (int k = 0; k + 1 < kMaxBranches; ++k) {
+        if (p->side[k])
+            (void)hipStreamDestroy(p->side[k]);
+        if (p->join_ev[k])
+            (void)hipEventDestroy(p->join_ev[k]);
+    }
+    if (p->fork_ev)
+        (void)hipEventDestroy(p->fork_ev);
     if (p->block >= 0)
         pool_release(ctx, p->block, nullptr);
     delete p;
@@ -1482,6 +1568,17 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
     }
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e == hipSuccess && kPlanBranches > 1) {
+        e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+        for (int k = 0; k + 1 < kPlanBranches && e == hipSuccess; ++k) {
+            e = hipStreamCreateWithFlags(&p->side[k], hipStreamNonBlocking);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&p->join_ev[k], hipEventDisableTiming);
+        }
+        if (e == hipSuccess)
+            p->branches = kPlanBranches;
+    }
+    plan_branches(p, p->branches);
     if (e != hipSuccess) {
         plan_free(ctx, p);
         return hip_fail(ctx, e);
