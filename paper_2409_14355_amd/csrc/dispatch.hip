@@ -11,7 +11,7 @@ namespace mpnl {
 
 #define MPNL_DECLARE(n)                                                                 \
     hipError_t path_launch_n##n(const dev::PathArgs &, int, int, hipStream_t);          \
-    hipError_t path_multi_launch_n##n(const dev::MultiArgs &, int, int, int, int, hipStream_t); \
+    hipError_t path_multi_launch_n##n(const dev::MultiArgs &, int, int, int, dim3, hipStream_t); \
     hipError_t path_bound_launch_n##n(const dev::PathArgs &, int, int, hipStream_t);    \
     hipError_t path_bound_multi_launch_n##n(const JobDev *, int, int, int, int, hipStream_t);
 MPNL_FOR_N(MPNL_DECLARE)
@@ -26,7 +26,7 @@ namespace {
 using namespace dev;
 
 typedef hipError_t (*PathLaunch)(const PathArgs &, int, int, hipStream_t);
-typedef hipError_t (*MultiLaunch)(const MultiArgs &, int, int, int, int, hipStream_t);
+typedef hipError_t (*MultiLaunch)(const MultiArgs &, int, int, int, dim3, hipStream_t);
 typedef hipError_t (*BoundLaunch)(const PathArgs &, int, int, hipStream_t);
 typedef hipError_t (*BoundMultiLaunch)(const JobDev *, int, int, int, int, hipStream_t);
 
@@ -63,8 +63,6 @@ PathArgs path_args(const SlotDev &sd, const float2 *yt, int T, int32_t *out)
     a.N = sd.N;
     a.K = sd.K;
     a.NP = sd.NP;
-    a.ipw = 1;
-    a.gmajor = 1;
     a.sigma2 = 1.f;
     a.clip = 0.f;
     return a;
@@ -101,12 +99,10 @@ hipError_t launch_path_search(const SlotDev &sd, const float2 *yt, int T, int32_
     }
     if ((long long)sd.S * T * groups > INT_MAX)
         return hipErrorInvalidValue;
-    // one-wavefront path groups, one a workgroup, group major (measured on
-    // MI355X, 16 users x 1200 x 14, 256 paths: 0.092 ms against 0.150 ms
-    // vector major; vector major needs four items a workgroup to reach
-    // 0.095 ms; 24 users x 3276 x 14: 0.253 against 0.270 at best)
-    a.ipw = 1;
-    a.gmajor = 1;
+    // one-wavefront path groups, one a workgroup, group major on a 2-D grid
+    // (measured on MI355X, 16 users x 1200 x 14, 256 paths: 0.085 ms; the
+    // same numbered vector major took 0.150 ms, and needed four items a
+    // workgroup to reach 0.095 ms; 24 users x 3276 x 14: 0.243 ms)
     hipError_t e = kPathLaunch[sd.N - 1](a, sd.bits, precision, st);
     if (e != hipSuccess || groups <= 1)
         return e;
@@ -173,7 +169,8 @@ hipError_t launch_path_search_multi(const JobDev *jobs_dev, int n_jobs, int tota
     const long long nvb = ((long long)total_items + ipw - 1) / ipw;  // workgroups per path group
     if (nvb * groups > INT_MAX)
         return hipErrorInvalidValue;
-    const int grid = (int)(nvb * groups);
+    // group major: grid (workgroups per group, groups); vector major: 1-D
+    const dim3 grid = gmajor ? dim3((unsigned)nvb, (unsigned)groups) : dim3((unsigned)(nvb * groups));
     hipError_t e = kMultiLaunch[N - 1](a, bits, precision, ipw * a.gw, grid, st);
     if (e != hipSuccess || groups == 1)
         return e;
