@@ -428,6 +428,15 @@ __device__ __forceinline__ constexpr float code_weight(int d)
 // pruned path has a metric strictly above the minimum.
 constexpr float kBoundPad = 1.0001f;
 
+// FP32 descents above this many users keep their decided symbols as half2
+// (descend).  Mixed FMAs issue slower than plain ones here: in the one-job
+// search at 16 users the float2 form (no spills) is 6% faster, at 24 users 1%.
+constexpr int kHalfStateN = 24;
+// ... and in the multi-job search, which holds more state: 40 cells of
+// 4..32 users in FP32, 121.6 M vectors/s with the float2 form, 127.3 M above
+// 24 users, 129.3 M above 16 users
+constexpr int kHalfStateNMulti = 16;
+
 // Received values of one descent: yt of the vector in depth order, read
 // where each depth needs it, from a wave-uniform pointer (scalar loads) ...
 struct YUniform {
@@ -472,13 +481,19 @@ struct RLanes {
 // stops once no lane with live = true has a metric at or below it (a NaN
 // metric counts as above; all lanes must take part).  FIRST: every rank is 1
 // (path 0), the choice code for higher ranks is left out.
-template <int N, int L, int PREC, bool FIRST = false, typename YF, typename RF>
+template <int N, int L, int PREC, bool FIRST = false, int HSN = kHalfStateN, typename YF, typename RF>
 __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_t *pw, float *decf, float prune,
                                          bool live)
 {
     float metric = 0.f;
     const uint64_t live_lanes = lane_mask(live);
-    float2 sv[N];                  // FP32: (s_I, s_Q) of the decided depths
+    // FP32: (s_I, s_Q) of the decided depths, as a float2, or above HSN
+    // users as a half2 (small odd integers, exact) that mixed
+    // FMAs widen exactly where they read it: the same products and sums in
+    // half the registers, for user counts where the float2 form spills
+    constexpr bool HS = PREC == PREC_FP32 && N > HSN;
+    float2 sv[HS ? 1 : N];
+    uint32_t sh[HS ? N : 1];
     uint32_t sa[N], sb[N];         // FP16 / BF16: packed (-s_I, s_Q) and (-s_Q, -s_I)
 #pragma unroll
     for (int d = 0; d < N; ++d) {
@@ -490,10 +505,21 @@ __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_
 #pragma unroll
             for (int e = 0; e < d; ++e) {
                 const float2 r = R.r(d * N + e);
-                zI = fmaf(-r.x, sv[e].x, zI);
-                zI = fmaf(r.y, sv[e].y, zI);
-                zQ = fmaf(-r.x, sv[e].y, zQ);
-                zQ = fmaf(-r.y, sv[e].x, zQ);
+                float sI, sQ;
+                if constexpr (HS) {
+                    uint32_t she = sh[e];
+                    asm("" : "+v"(she));  // a fresh value per depth: widened where used, not kept widened
+                    const half2_t se = __builtin_bit_cast(half2_t, she);
+                    sI = (float)se.x;
+                    sQ = (float)se.y;
+                } else {
+                    sI = sv[e].x;
+                    sQ = sv[e].y;
+                }
+                zI = fmaf(-r.x, sI, zI);
+                zI = fmaf(r.y, sQ, zI);
+                zQ = fmaf(-r.x, sQ, zQ);
+                zQ = fmaf(-r.y, sI, zQ);
             }
         } else if constexpr (PREC == PREC_FP16) {
 #pragma unroll
@@ -546,7 +572,12 @@ __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_
         if (d + 1 < N && (lane_mask(metric <= prune) & live_lanes) == 0)
             break;
         const float sI = level_of<L>(mI), sQ = level_of<L>(mQ);
-        if constexpr (PREC == PREC_FP32) {
+        if constexpr (HS) {
+            half2_t hs;
+            hs.x = (_Float16)sI;
+            hs.y = (_Float16)sQ;
+            sh[d] = __builtin_bit_cast(uint32_t, hs);
+        } else if constexpr (PREC == PREC_FP32) {
             sv[d] = make_float2(sI, sQ);
         } else if constexpr (PREC == PREC_FP16) {
             half2_t ha, hb;  // small odd integers, exact
@@ -625,8 +656,9 @@ __device__ __forceinline__ int block_argmin(float bm, int br, int W, float *sm, 
 // Every lane of the workgroup calls this (it may synchronise the workgroup);
 // lanes of an inactive vector do no work.
 // b0 / b0d: path 0's metric and packed decisions from the pruning record
-// (b0d null: no record, path 0 is searched like the others).
-template <int N, int L, int PREC>
+// (b0d null: no record, path 0 is searched like the others).  HSN: descend's
+// half2 threshold.
+template <int N, int L, int PREC, int HSN = kHalfStateN>
 __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cptr<float> rl,
                                               cptr<uint32_t> rq, const uint8_t *Pbase,
                                               const uint16_t *order, int K, int NP, int group,
@@ -655,7 +687,8 @@ __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cp
         for (int w = 0; w < NW; ++w)
             pw[w] = valid ? Pw[(size_t)r * nw + w] : 0x01010101u;
         const bool known = valid && r == 0 && b0d != nullptr;
-        const float m = descend<N, L, PREC>(YUniform{yv}, RUniform{dg, rl, rq}, pw, decf, prune, valid && !known);
+        const float m = descend<N, L, PREC, false, HSN>(YUniform{yv}, RUniform{dg, rl, rq}, pw, decf, prune,
+                                                         valid && !known);
         if (valid) {
             bm = known ? b0 : m;
             br = r;
@@ -933,10 +966,10 @@ path_search_multi_kernel(MultiArgs a)
     const float b0 = j.bound ? uniform_ptr(j.bound + v)[0] : INFINITY;
     const float *b0d = j.bound ? j.bound + (size_t)j.S * j.T + v * NW : nullptr;
     float *part = a.groups > 1 ? j.part + (v * a.groups + g) * (2 + NW) : nullptr;
-    search_vector<N, L, PREC>(uniform_ptr(j.yt + v * N), uniform_ptr(j.diag + sN), uniform_ptr(j.rlat + sN * N), rq,
-                              j.P + (size_t)s * j.K * j.NP, j.order ? j.order + (size_t)s * j.K : nullptr, j.K,
-                              j.NP, g, j.permd + sN, j.out + v * N, part, sm, sr, W, (int)threadIdx.x - q * W,
-                              active, b0, b0d);
+    search_vector<N, L, PREC, kHalfStateNMulti>(
+        uniform_ptr(j.yt + v * N), uniform_ptr(j.diag + sN), uniform_ptr(j.rlat + sN * N), rq,
+        j.P + (size_t)s * j.K * j.NP, j.order ? j.order + (size_t)s * j.K : nullptr, j.K, j.NP, g, j.permd + sN,
+        j.out + v * N, part, sm, sr, W, (int)threadIdx.x - q * W, active, b0, b0d);
 }
 
 // Best of the path groups of every received vector of a multi-job launch.
