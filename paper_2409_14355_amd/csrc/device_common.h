@@ -394,7 +394,7 @@ struct PathArgs {
     const float2 *yt;      // (T, S, N) rotated received vectors, lattice units
     const float4 *diag;    // (S, N) (a^2 or 1, R_ll == 0, 1/a or 1, R_ll)
     const float2 *rlat;    // (S, N, N) R' transposed, lattice units: [d][e] = coefficient of s_e in row d
-    const uint32_t *rq;    // (S, N, N) half2 / bf16x2 of rlat, or null
+    const uint32_t *rq;    // (S, N, N, 2) packed FP16 / BF16 pairs of rlat (SlotDev::rlat_h), or null
     const int32_t *permd;  // (S, N)
     const uint8_t *P;      // (S, K, NP)
     const uint16_t *order; // (S, K) path run by each lane, or null (identity)
@@ -452,14 +452,16 @@ struct YLanes {
 
 // The subcarrier's triangular factor as the descent reads it: the diagonal
 // record (a^2, R_ll == 0 flag, ...) per depth and R' transposed (rl, FP32;
-// rq, packed FP16 / BF16), through a wave-uniform pointer (scalar loads) ...
+// rq, packed FP16 / BF16 pairs (x, y), (y, -x): with the decided symbol
+// packed as (-s_I, s_Q), one dot2 with each gives the I and the Q term),
+// through a wave-uniform pointer (scalar loads) ...
 struct RUniform {
     cptr<float> dg, rl;
     cptr<uint32_t> rq;
     __device__ __forceinline__ float gw(int d) const { return dg[4 * d]; }
     __device__ __forceinline__ float gzero(int d) const { return dg[4 * d + 1]; }
     __device__ __forceinline__ float2 r(int i) const { return ld2(rl, i); }
-    __device__ __forceinline__ uint32_t q(int i) const { return rq[i]; }
+    __device__ __forceinline__ uint2 q(int i) const { return make_uint2(rq[2 * i], rq[2 * i + 1]); }
 };
 // ... or through a pointer of each lane's own subcarrier (vector loads).
 struct RLanes {
@@ -468,7 +470,7 @@ struct RLanes {
     __device__ __forceinline__ float gw(int d) const { return dg[4 * d]; }
     __device__ __forceinline__ float gzero(int d) const { return dg[4 * d + 1]; }
     __device__ __forceinline__ float2 r(int i) const { return ((const float2 *)rl)[i]; }
-    __device__ __forceinline__ uint32_t q(int i) const { return rq[i]; }
+    __device__ __forceinline__ uint2 q(int i) const { return ((const uint2 *)rq)[i]; }
 };
 
 // One SIC descent driven by the position vector in pw, left-looking: the
@@ -494,7 +496,7 @@ __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_
     constexpr bool HS = PREC == PREC_FP32 && N > HSN;
     float2 sv[HS ? 1 : N];
     uint32_t sh[HS ? N : 1];
-    uint32_t sa[N], sb[N];         // FP16 / BF16: packed (-s_I, s_Q) and (-s_Q, -s_I)
+    uint32_t sa[N];                // FP16 / BF16: packed (-s_I, s_Q)
 #pragma unroll
     for (int d = 0; d < N; ++d) {
         const int k = (pw[d >> 2] >> ((d & 3) * 8)) & 0xff;
@@ -524,16 +526,18 @@ __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_
         } else if constexpr (PREC == PREC_FP16) {
 #pragma unroll
             for (int e = 0; e < d; ++e) {
-                const half2_t r = __builtin_bit_cast(half2_t, R.q(d * N + e));
-                zI = __builtin_amdgcn_fdot2(r, __builtin_bit_cast(half2_t, sa[e]), zI, false);
-                zQ = __builtin_amdgcn_fdot2(r, __builtin_bit_cast(half2_t, sb[e]), zQ, false);
+                const uint2 r = R.q(d * N + e);
+                const half2_t se = __builtin_bit_cast(half2_t, sa[e]);
+                zI = __builtin_amdgcn_fdot2(__builtin_bit_cast(half2_t, r.x), se, zI, false);
+                zQ = __builtin_amdgcn_fdot2(__builtin_bit_cast(half2_t, r.y), se, zQ, false);
             }
         } else {
 #pragma unroll
             for (int e = 0; e < d; ++e) {
-                const bf162_t r = __builtin_bit_cast(bf162_t, R.q(d * N + e));
-                zI = __builtin_amdgcn_fdot2_f32_bf16(r, __builtin_bit_cast(bf162_t, sa[e]), zI, false);
-                zQ = __builtin_amdgcn_fdot2_f32_bf16(r, __builtin_bit_cast(bf162_t, sb[e]), zQ, false);
+                const uint2 r = R.q(d * N + e);
+                const bf162_t se = __builtin_bit_cast(bf162_t, sa[e]);
+                zI = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf162_t, r.x), se, zI, false);
+                zQ = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf162_t, r.y), se, zQ, false);
             }
         }
         float mI, mQ, e;  // the chosen point and its squared distance
@@ -580,21 +584,15 @@ __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_
         } else if constexpr (PREC == PREC_FP32) {
             sv[d] = make_float2(sI, sQ);
         } else if constexpr (PREC == PREC_FP16) {
-            half2_t ha, hb;  // small odd integers, exact
+            half2_t ha;  // small odd integers, exact
             ha.x = (_Float16)(-sI);
             ha.y = (_Float16)sQ;
-            hb.x = (_Float16)(-sQ);
-            hb.y = (_Float16)(-sI);
             sa[d] = __builtin_bit_cast(uint32_t, ha);
-            sb[d] = __builtin_bit_cast(uint32_t, hb);
         } else {
-            bf162_t ha, hb;
+            bf162_t ha;
             ha.x = (__bf16)(-sI);
             ha.y = (__bf16)sQ;
-            hb.x = (__bf16)(-sQ);
-            hb.y = (__bf16)(-sI);
             sa[d] = __builtin_bit_cast(uint32_t, ha);
-            sb[d] = __builtin_bit_cast(uint32_t, hb);
         }
     }
     return (metric == metric) ? metric : INFINITY;
@@ -718,18 +716,19 @@ __device__ __forceinline__ void search_vector(cptr<float> yv, cptr<float> dg, cp
     }
 }
 
-// Occupancy of the path searches.  The descent is bound by the latency of
-// its per-depth scalar loads of R and y as much as by VALU issue, so more
-// resident wavefronts pay even where the decided symbols of the deeper depths
-// spill to scratch: in FP32 eight wavefronts per SIMD (64 VGPRs; 16 users:
-// 0.128 -> 0.116 ms per 1200 x 14 launch, 24 users: 0.477 -> 0.352 ms per
-// 3276 x 14, before the one-wavefront path groups).  FP16 / BF16 keep more
-// state per lane (packed operands and conversions) and run six (80 VGPRs):
-// the 40-cell FP16 batch takes 4.47 ms of path search at six against 5.76 ms
-// at eight; the one-job 24-user slot 0.250 against 0.262 ms (16 users: equal).
+// Occupancy of the path searches: eight wavefronts per SIMD (64 VGPRs) in
+// every precision.  The descent is bound by the latency of its per-depth
+// scalar loads of R and y as much as by VALU issue, so more resident
+// wavefronts pay even where the decided symbols of the deeper depths spill
+// to scratch (FP32, 16 users: 0.128 -> 0.116 ms per 1200 x 14 launch; 24
+// users: 0.477 -> 0.352 ms per 3276 x 14, before the one-wavefront path
+// groups).  FP16 / BF16 keep one packed register per decided depth (the
+// paired R copy); with two they ran six wavefronts, and with one, eight
+// against six measured: 40 cells 3.71 against 3.83 ms of path stage, the
+// 24-user slot 0.222 against 0.229 ms, 16 users equal.
 template <int PREC>
 struct PathOccupancy {
-    static constexpr int waves = PREC == PREC_FP32 ? 8 : 6;
+    static constexpr int waves = 8;
 };
 
 // Work item (vector, path group) of slot q of this workgroup, for `groups`
@@ -770,7 +769,7 @@ path_search_kernel(PathArgs a)
     const int s = lb / a.T, t = lb - s * a.T;
     const size_t sN = (size_t)s * N;
     const size_t v = (size_t)t * a.S + s;
-    cptr<uint32_t> rq = a.rq ? uniform_ptr(a.rq + sN * N) : nullptr;
+    cptr<uint32_t> rq = a.rq ? uniform_ptr(a.rq + 2 * sN * N) : nullptr;
     float *part = a.part ? a.part + (v * groups + g) * (2 + (N + 3) / 4) : nullptr;
     const float b0 = a.bound ? uniform_ptr(a.bound + v)[0] : INFINITY;
     const float *b0d = a.bound ? a.bound + (size_t)a.S * a.T + v * ((N + 3) / 4) : nullptr;
@@ -962,7 +961,7 @@ path_search_multi_kernel(MultiArgs a)
     const int s = li / j.T, t = li - s * j.T;
     const size_t sN = (size_t)s * N;
     const size_t v = (size_t)t * j.S + s;
-    cptr<uint32_t> rq = j.rq ? uniform_ptr(j.rq + sN * N) : nullptr;
+    cptr<uint32_t> rq = j.rq ? uniform_ptr(j.rq + 2 * sN * N) : nullptr;
     const float b0 = j.bound ? uniform_ptr(j.bound + v)[0] : INFINITY;
     const float *b0d = j.bound ? j.bound + (size_t)j.S * j.T + v * NW : nullptr;
     float *part = a.groups > 1 ? j.part + (v * a.groups + g) * (2 + NW) : nullptr;
@@ -1010,7 +1009,7 @@ __device__ __forceinline__ void bound_body(const float2 *yt, const float4 *diag,
 #pragma unroll
     for (int d = 0; d < N; ++d)
         yl.v[d] = yv[d];
-    const RLanes R{(const float *)(diag + sN), (const float *)(rlat + sN * N), rq ? rq + sN * N : nullptr};
+    const RLanes R{(const float *)(diag + sN), (const float *)(rlat + sN * N), rq ? rq + 2 * sN * N : nullptr};
     uint32_t pw[NW];
     float decf[NW];
 #pragma unroll

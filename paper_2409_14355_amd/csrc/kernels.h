@@ -16,8 +16,8 @@ struct SlotDev {
     float2 *roff;          // (S, N, N)  [d][d'] = R[N-1-d'][N-1-d] for d' > d
     float2 *rlat;          // (S, N, N)  the same entries in lattice units, times Delta / a_{d'},
                            //            transposed: [d'][d] (row d', term of depth d < d')
-    uint32_t *rlat_h;      // (S, N, N)  rlat as half2 (MPNL_PREC_FP16)
-    uint32_t *rlat_b;      // (S, N, N)  rlat as bf16x2 (MPNL_PREC_BF16)
+    uint32_t *rlat_h;      // (S, N, N, 2)  rlat entry (x, y) as half2 pairs (x, y), (y, -x) (MPNL_PREC_FP16)
+    uint32_t *rlat_b;      // (S, N, N, 2)  the same as bf16x2 pairs (MPNL_PREC_BF16)
     float4 *diag;          // (S, N)     (a^2 or 1, R_ll == 0, 1/a or 1, R_ll), a = R_ll Delta
     double *wd;            // (S, N)     R_ll^2 from the float64 pivot norm
     int32_t *permd;        // (S, N)     original user detected at depth d
@@ -32,7 +32,7 @@ struct SlotDev {
 struct JobDev {
     const float2 *yt;      // (T, S, N) rotated received vectors, depth order, lattice units
     const float2 *rlat;
-    const uint32_t *rq;    // packed FP16 / BF16 copy of rlat for reduced precision, else null
+    const uint32_t *rq;    // packed FP16 / BF16 pairs of rlat for reduced precision, else null
     const float4 *diag;
     const int32_t *permd;
     const uint8_t *P;

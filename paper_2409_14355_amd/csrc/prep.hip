@@ -167,8 +167,10 @@ __device__ __forceinline__ void sqrd_body(const SqrdArgs &a, int pair)
                 const float lx = col[m].x * sc, ly = col[m].y * sc;
                 a.sd.roff[o] = col[m];
                 a.sd.rlat[ot] = make_float2(lx, ly);
-                a.sd.rlat_h[ot] = pack_half2(lx, ly);
-                a.sd.rlat_b[ot] = bf16_bits(lx) | (bf16_bits(ly) << 16);
+                a.sd.rlat_h[2 * ot] = pack_half2(lx, ly);
+                a.sd.rlat_h[2 * ot + 1] = pack_half2(ly, -lx);
+                a.sd.rlat_b[2 * ot] = bf16_bits(lx) | (bf16_bits(ly) << 16);
+                a.sd.rlat_b[2 * ot + 1] = bf16_bits(ly) | (bf16_bits(-lx) << 16);
             }
         }
     }

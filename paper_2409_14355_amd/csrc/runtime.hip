@@ -341,8 +341,8 @@ SlotLayout slot_layout(int S, int M, int N, int K, int NP, bool rec_global, bool
     put(L.Qd, (size_t)S * M * N * sizeof(float2));
     put(L.roff, sNN * sizeof(float2));
     put(L.rlat, sNN * sizeof(float2));
-    put(L.rlat_h, sNN * sizeof(uint32_t));
-    put(L.rlat_b, sNN * sizeof(uint32_t));
+    put(L.rlat_h, 2 * sNN * sizeof(uint32_t));
+    put(L.rlat_b, 2 * sNN * sizeof(uint32_t));
     put(L.diag, (size_t)S * N * sizeof(float4));
     put(L.wd, (size_t)S * N * sizeof(double));
     put(L.permd, (size_t)S * N * sizeof(int32_t));
