@@ -22,6 +22,7 @@
  *   P   : (K, N)      uint8 position vectors, depth order, ranks 1..|Q|
  */
 #include <complex.h>
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -364,9 +365,14 @@ int orc_sqrd(const cplx *H, int M, int N, cplx *Q, cplx *R, int32_t *perm,
 /* before transmission (Sec. II).  Reading taken: depth d detects row       */
 /* l = N-1-d of R; a position vector p (p_d in 1..|Q|) asks for the p_d-th  */
 /* closest symbol at depth d; its cost is                                   */
-/*      score(p) = sum_d w_d (p_d - 1),   w_d = R_{l,l}^2,                   */
-/* summed in depth order.  The set is the first K = min(N_p, |Q|^N) vectors */
-/* in (score ascending, p lexicographic ascending) order.                   */
+/*      score(p) = sum_d c_d (p_d - 1),   c_d = rint(2^20 w_d / max_e w_e),  */
+/*      w_d = R_{l,l}^2,                                                    */
+/* integer depth costs: each weight relative to the largest, in units of   */
+/* 2^-20, rounded to the nearest integer (ties to even); a weight that is  */
+/* not a number, or a largest weight that is not positive and finite,      */
+/* gives cost 0.  Sums of such integers are exact, so ties are exact ties. */
+/* The set is the first K = min(N_p, |Q|^N) vectors in (score ascending,   */
+/* p lexicographic ascending) order.                                        */
 /*                                                                          */
 /* Best-first search: pop the smallest vector, emit it, push its canonical  */
 /* children p + e_j for every j >= last(p) with p_j < |Q|, where last(p) is */
@@ -379,11 +385,27 @@ typedef struct {
     uint8_t p[ORC_MAXN];
 } pv_entry;
 
-static double pv_score(const double *w_depth, const uint8_t *p, int N)
+#define ORC_COST_BITS 20
+
+/* c_d from w_d (integers held in doubles, exact). */
+static void depth_costs(const double *w_depth, int N, double *c)
+{
+    double wmax = 0.0;
+    for (int d = 0; d < N; d++)
+        if (w_depth[d] > wmax)
+            wmax = w_depth[d];
+    const double one = (double)(1 << ORC_COST_BITS);
+    for (int d = 0; d < N; d++) {
+        const double x = (w_depth[d] / wmax) * one;
+        c[d] = (wmax > 0.0 && wmax <= DBL_MAX && x >= 0.0 && x <= one) ? rint(x) : 0.0;
+    }
+}
+
+static double pv_score(const double *c, const uint8_t *p, int N)
 {
     double s = 0.0;
     for (int d = 0; d < N; d++)
-        s += w_depth[d] * (double)(p[d] - 1);
+        s += c[d] * (double)(p[d] - 1);
     return s;
 }
 
@@ -453,12 +475,14 @@ int orc_position_set(const double *w_depth, int N, int nq, int n_paths,
     int K = (long)n_paths < total ? n_paths : (int)total;
     long cap = (long)(K + 1) * N + 1;
     pv_entry *h = malloc(sizeof(pv_entry) * cap);
+    double c[ORC_MAXN];
+    depth_costs(w_depth, N, c);
     int n = 0;
     pv_entry root;
     memset(&root, 0, sizeof(root));
     for (int d = 0; d < N; d++)
         root.p[d] = 1;
-    root.score = pv_score(w_depth, root.p, N);
+    root.score = pv_score(c, root.p, N);
     heap_push(h, &n, &root, N);
     double last_score = 0.0;
     for (int k = 0; k <= K && n > 0; k++) {
@@ -478,10 +502,10 @@ int orc_position_set(const double *w_depth, int N, int nq, int n_paths,
                 last = d;
         for (int j = last; j < N; j++)
             if (e.p[j] < nq) {
-                pv_entry c = e;
-                c.p[j]++;
-                c.score = pv_score(w_depth, c.p, N);
-                heap_push(h, &n, &c, N);
+                pv_entry ch = e;
+                ch.p[j]++;
+                ch.score = pv_score(c, ch.p, N);
+                heap_push(h, &n, &ch, N);
             }
     }
     if (K == total && boundary_margin)
@@ -510,13 +534,15 @@ int orc_position_set_brute(const double *w_depth, int N, int nq, int n_paths,
     if (total > (1L << 22) || n_paths < 1)
         return -1;
     pv_entry *all = malloc(sizeof(pv_entry) * total);
+    double c[ORC_MAXN];
+    depth_costs(w_depth, N, c);
     uint8_t cur[ORC_MAXN];
     for (int d = 0; d < N; d++)
         cur[d] = 1;
     for (long v = 0; v < total; v++) {
         memset(&all[v], 0, sizeof(pv_entry));
         memcpy(all[v].p, cur, (size_t)N);
-        all[v].score = pv_score(w_depth, cur, N);
+        all[v].score = pv_score(c, cur, N);
         int d = N - 1;
         while (d >= 0 && cur[d] == nq) {
             cur[d] = 1;

@@ -141,6 +141,26 @@ __device__ __forceinline__ double lane_read(double x, int l)
     return __longlong_as_double((long long)(lo | (hi << 32)));
 }
 
+// 64-bit words through the 32-bit moves above, one half at a time.
+__device__ __forceinline__ uint64_t lane_join(uint32_t lo, uint32_t hi) { return (uint64_t)lo | ((uint64_t)hi << 32); }
+__device__ __forceinline__ uint64_t lane_xor_n(uint64_t x, int s)
+{
+    return lane_join(lane_xor_n((uint32_t)x, s), lane_xor_n((uint32_t)(x >> 32), s));
+}
+__device__ __forceinline__ uint64_t lane_read(uint64_t x, int l)
+{
+    return lane_join(lane_read((uint32_t)x, l), lane_read((uint32_t)(x >> 32), l));
+}
+template <int S>
+__device__ __forceinline__ void lane_pair(uint64_t x, uint64_t &lo, uint64_t &hi)
+{
+    uint32_t l0, h0, l1, h1;
+    lane_pair<S>((uint32_t)x, l0, h0);
+    lane_pair<S>((uint32_t)(x >> 32), l1, h1);
+    lo = lane_join(l0, l1);
+    hi = lane_join(h0, h1);
+}
+
 // x of lane 63 - lane: mirror inside each row of 16, then swap the rows.
 __device__ __forceinline__ uint32_t lane_mirror(uint32_t x)
 {
@@ -152,6 +172,10 @@ __device__ __forceinline__ double lane_mirror(double x)
     const uint64_t u = (uint64_t)__double_as_longlong(x);
     const uint64_t lo = lane_mirror((uint32_t)u), hi = lane_mirror((uint32_t)(u >> 32));
     return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+__device__ __forceinline__ uint64_t lane_mirror(uint64_t x)
+{
+    return lane_join(lane_mirror((uint32_t)x), lane_mirror((uint32_t)(x >> 32)));
 }
 
 __device__ __forceinline__ int gray_code(int m) { return m ^ (m >> 1); }
@@ -171,6 +195,22 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks)
     const int xcd = bid % X, local = bid / X;
     const int q = nblocks / X, rem = nblocks % X;
     return xcd * q + min(xcd, rem) + local;
+}
+
+// a2 depth costs.  The cost of a position vector is sum_d c_d (p_d - 1) in
+// integers, c_d = rint(w_d / max_e w_e * 2^kCostBits): the depth weights of
+// the subcarrier scaled so that the largest becomes 2^kCostBits, rounded to
+// the nearest integer (ties to even).  Sums stay below 2^31 for 32 depths and
+// ranks up to 64, so costs and their comparisons are exact.  A weight that is
+// not a number, or a subcarrier whose largest weight is not a positive finite
+// number, gives cost 0.
+constexpr int kCostBits = 20;
+__device__ __forceinline__ uint32_t cost_unit(double w, double wmax)
+{
+    const double x = (w / wmax) * (double)(1 << kCostBits);
+    return (wmax > 0.0 && wmax <= 1.7976931348623157e308 && x >= 0.0 && x <= (double)(1 << kCostBits))
+               ? (uint32_t)rint(x)
+               : 0u;
 }
 
 // a2 arguments (position-vector set kernels)

@@ -2,23 +2,24 @@
 // E wavefronts, one list entry per lane.
 //
 // Same definition as posvec_kernel (prep.hip): the K cheapest position
-// vectors in (score, lexicographic) order, score = sum_d w_d (p_d - 1)
-// accumulated in depth order in float64.  Depth by depth the list of the K
-// cheapest prefixes A is extended by rank doubling:
+// vectors in (cost, lexicographic) order, cost = sum_d c_d (p_d - 1) in
+// exact integers (cost_unit).  Depth by depth the list of the K cheapest
+// prefixes A is extended by rank doubling:
 //     U_0 = A (rank 0 at this depth),   U_{j+1} = topK(U_j  U  raise(U_j, 2^j)),
-// where raise(., c) adds c to the last rank (score parent + w_d * k, always
-// recomputed from the parent), so U_j holds the K cheapest extensions with
-// rank below 2^j; log2 |Q| merges cover every rank.  The top K of a union is
-// the top K of the unions of top Ks, which makes each step exact.
+// where raise(., c) adds c to the last rank (cost parent + c_d k), so U_j
+// holds the K cheapest extensions with rank below 2^j; log2 |Q| merges cover
+// every rank.  The top K of a union is the top K of the unions of top Ks,
+// which makes each step exact, and raising adds the same c_d 2^j to every
+// entry, so the raised list stays sorted.
 // Every merge is a bitonic network: thread g holds entry g of the list
 // (g = 64 w + lane for wavefront w).  One half-cleaner stage compares U_j
 // with the reversed raised list, then log2(64 E) compare-exchange stages sort
 // the K smallest.  The half cleaner and each stage across wavefronts go
 // through LDS (alternating buffers, one barrier each), the stages inside a
-// wavefront use DPP / row-swap lane exchanges.  An entry
-// is (score, packed) with packed = parent position (12 bits) | k (6 bits)
-// << 12 | lexical rank of the parent (14 bits) << 18, so the key
-// (score, parent rank, k) compares as (score, packed).
+// wavefront use DPP / row-swap lane exchanges.  An entry is one 64-bit key,
+// cost << 32 | packed with packed = parent position (12 bits) | k (6 bits)
+// << 12 | lexical rank of the parent (14 bits) << 18, so that (cost, parent
+// rank, k) compares as one unsigned integer.
 #include "device_common.h"
 
 #include <algorithm>
@@ -27,60 +28,44 @@ namespace mpnl {
 namespace dev {
 namespace {
 
-constexpr uint32_t kSentinel = 0xffffffffu;
+constexpr uint64_t kNone = ~0ull;  // empty list entry: above every key
 
-// (score, packed) order.  Branch-free (a short-circuit form compiles to
-// divergent branches).  The whole packed word is compared: its low 12 bits
-// (parent position) only matter between words with equal (parent rank, k),
-// which no two distinct entries of one list share.
-__device__ __forceinline__ bool key_lt(double as, uint32_t ap, double bs, uint32_t bp)
+__device__ __forceinline__ uint64_t pkey(uint32_t cost, uint32_t packed)
 {
-    return (as < bs) | ((as == bs) & (ap < bp));
+    return ((uint64_t)cost << 32) | packed;
 }
+__device__ __forceinline__ uint32_t key_cost(uint64_t k) { return (uint32_t)(k >> 32); }
+__device__ __forceinline__ uint32_t key_packed(uint64_t k) { return (uint32_t)k; }
 
-// parent + w k, product and sum rounded separately (no fused multiply-add)
-__device__ __forceinline__ double cand_score_r(double parent, double w, int k)
-{
-#pragma clang fp contract(off)
-    return parent + w * (double)k;
-}
-
-// Compare-exchange of entry (cs, cp) with the entry of lane ^ S, keeping the
-// smaller key in the lower lane when `asc`, the larger otherwise.  At
-// distance 16 or 32 one swap gives both entries of the pair and the lane's
-// side picks; below, the partner's entry comes from DPP.
+// Compare-exchange of key c with the key of lane ^ S, keeping the smaller in
+// the lower lane when `asc`, the larger otherwise.  At distance 16 or 32 one
+// swap gives both keys of the pair and the lane's side picks; below, the
+// partner's key comes from DPP.
 template <int S>
-__device__ __forceinline__ void lane_stage(double &cs, uint32_t &cp, bool asc)
+__device__ __forceinline__ void lane_stage(uint64_t &c, bool asc)
 {
     if constexpr (S >= 16) {
-        double ls, hs;
-        uint32_t lp, hp;
-        lane_pair<S>(cs, ls, hs);
-        lane_pair<S>(cp, lp, hp);
+        uint64_t lo, hi;
+        lane_pair<S>(c, lo, hi);
         const bool upper = (threadIdx.x & (unsigned)S) != 0;
-        const bool take_hi = (key_lt(hs, hp, ls, lp) != upper) == asc;
-        cs = take_hi ? hs : ls;
-        cp = take_hi ? hp : lp;
+        c = ((hi < lo) != upper) == asc ? hi : lo;
     } else {
-        const double os = lane_xor_n(cs, S);
-        const uint32_t op = lane_xor_n(cp, S);
+        const uint64_t o = lane_xor_n(c, S);
         const bool lower = (threadIdx.x & (unsigned)S) == 0;
-        const bool take = (lower == asc) == key_lt(os, op, cs, cp);
-        cs = take ? os : cs;
-        cp = take ? op : cp;
+        c = ((lower == asc) == (o < c)) ? o : c;
     }
 }
 
 // The same at a run-time distance (constant after unrolling).
-__device__ __forceinline__ void lane_stage_n(double &cs, uint32_t &cp, int s, bool asc)
+__device__ __forceinline__ void lane_stage_n(uint64_t &c, int s, bool asc)
 {
     switch (s) {
-    case 1: lane_stage<1>(cs, cp, asc); break;
-    case 2: lane_stage<2>(cs, cp, asc); break;
-    case 4: lane_stage<4>(cs, cp, asc); break;
-    case 8: lane_stage<8>(cs, cp, asc); break;
-    case 16: lane_stage<16>(cs, cp, asc); break;
-    default: lane_stage<32>(cs, cp, asc); break;
+    case 1: lane_stage<1>(c, asc); break;
+    case 2: lane_stage<2>(c, asc); break;
+    case 4: lane_stage<4>(c, asc); break;
+    case 8: lane_stage<8>(c, asc); break;
+    case 16: lane_stage<16>(c, asc); break;
+    default: lane_stage<32>(c, asc); break;
     }
 }
 
@@ -101,26 +86,22 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v)
 template <int E>
 struct PosLds {
     static constexpr int KP = 64 * E;
-    double scA[KP];      // scores of list A by position
-    double xs[2][2][KP]; // exchange: [buffer][Z | B] scores
-    uint32_t xp[2][2][KP];
-    double bcs[2];       // broadcast of entry K-1 of Z
-    uint32_t bcp[2];
-    uint32_t cnt[KP];    // children per parent lexical rank
-    uint32_t run[KP];    // exclusive prefix of cnt inside each wavefront
-    uint32_t wsum[E];    // cnt total of each wavefront
-    uint32_t ap0;        // packed word of entry 0 of A
-    uint32_t apK1;       // packed word of entry K - 1 of A
+    uint64_t xk[2][2][KP]; // exchange: [buffer][Z | B] keys
+    uint64_t bck[2];       // broadcast of entry K-1 of Z
+    uint64_t akK1;         // key of entry K - 1 of A
+    uint32_t scA[KP];      // costs of list A by position
+    uint32_t cnt[KP];      // children per parent lexical rank
+    uint32_t run[KP];      // exclusive prefix of cnt inside each wavefront
+    uint32_t wsum[E];      // cnt total of each wavefront
+    uint32_t ap0;          // packed word of entry 0 of A
 };
 
 // LDS of one workgroup: PosLds, then N * KP back pointers per depth, 16 bits
-// each (parent position | k << 8).  For 256 paths and N = 16 that is 24 KB,
-// so six workgroups fit a compute unit and a 1200-subcarrier slot runs in a
+// each (parent position | k << 8).  For 256 paths and N = 16 that is 20 KB,
+// so eight workgroups fit a compute unit and a 1200-subcarrier slot runs in a
 // single round of workgroups.  REC_LDS = false: the back pointers live in
-// global memory (PosArgs::rec16) and the LDS holds PosLds only (16 KB for 256
-// paths, eight workgroups a compute unit), for slots where the larger count
-// saves a round (24 users: 28 KB, five a compute unit, 3276 subcarriers in
-// three rounds; without the pointers two).
+// global memory (PosArgs::rec16) and the LDS holds PosLds only (12 KB for 256
+// paths), for slots where the larger count saves a round.
 template <int E, bool REC_LDS = true>
 constexpr size_t pos_lds_bytes(int N)
 {
@@ -131,141 +112,115 @@ template <int E, bool REC_LDS = true>
 __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned char *smem)
 {
     constexpr int KP = 64 * E;
-    constexpr double INF = (double)INFINITY;
     PosLds<E> &sh = *(PosLds<E> *)smem;
     uint16_t *rec = REC_LDS ? (uint16_t *)(smem + sizeof(PosLds<E>)) : a.rec16 + (size_t)s * a.N * KP;
     const int g = (int)threadIdx.x;  // list entry of this lane
     const int lane = g & 63, wv = g >> 6;
     const int K = a.K, N = a.N, nq = a.nq;
 
-    double As = g == 0 ? 0.0 : INF;
-    uint32_t Ap = g == 0 ? 0u : kSentinel;
-    sh.scA[g] = As;
+    uint64_t Ak = g == 0 ? 0ull : kNone;  // the root: cost 0, packed 0
+    sh.scA[g] = key_cost(Ak);
     sh.cnt[g] = 0;
     if (g == 0)
         sh.ap0 = 0u;
     if (g == K - 1)
-        sh.apK1 = Ap;
-    // the weights of all depths, lane d holding w_d (N <= 32), read per
-    // depth from a register instead of a dependent load
+        sh.akK1 = Ak;
+    // the depth costs, lane d holding c_d (N <= 32), read per depth from a
+    // register instead of a dependent load
     const double wl = lane < N ? a.w[(size_t)s * N + lane] : 0.0;
+    double wmax = wl;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1)
+        wmax = fmax(wmax, lane_xor_n(wmax, o));  // every lane: the largest weight
+    const uint32_t cl = cost_unit(wl, wmax);
     __syncthreads();
 
     int buf = 0;
     for (int d = 0; d < N; ++d) {
-        const double w = lane_read(wl, d);
-        double Zs = As;
-        uint32_t Zp = Ap;
-        const double a0s = sh.scA[0];
+        const uint32_t c = lane_read(cl, d);
+        uint64_t Z = Ak;
+        const uint32_t a0s = sh.scA[0];
         const uint32_t a0p = sh.ap0;
         // A full list that not even the cheapest entry with rank 2 at this
         // depth (entry 0 raised by one) can enter: every prefix extends by
-        // rank 1 only, so positions, scores and lexical ranks stay as they
+        // rank 1 only, so positions, costs and lexical ranks stay as they
         // are and only the back pointers (parent = itself, k = 0) are
         // written; no LDS state changes, no barrier.  (The merge loop below
         // would stop at its first check and the rank pass reproduce the
         // ranks.)  The decision reads LDS written before the last barrier,
         // so every lane takes it alike.
         if (d > 0) {
-            const double lastS = sh.scA[K - 1];
-            if (lastS < INF && !key_lt(cand_score_r(a0s, w, 1), (a0p & 0xfffc0fffu) | (1u << 12), lastS, sh.apK1)) {
-                if (As < INF)
+            const uint64_t last = sh.akK1;
+            if (last != kNone && !(pkey(a0s + c, (a0p & 0xfffc0fffu) | (1u << 12)) < last)) {
+                if (Ak != kNone)
                     rec[(size_t)d * KP + g] = (uint16_t)(g & 0xff);
                 continue;
             }
         }
         // The first depth extends the root only: its children k = 0 .. |Q|-1
-        // are already in key order (scores non-decreasing in k, equal scores
+        // are already in key order (costs non-decreasing in k, equal costs
         // ordered by k), so entry g is child g and no merge is needed.
-        if (d == 0) {
-            const bool in = g < min(nq, K);
-            Zs = in ? cand_score_r(a0s, w, g) : INF;
-            Zp = in ? ((uint32_t)g << 12) : kSentinel;
-        }
+        if (d == 0)
+            Z = g < min(nq, K) ? pkey(c * (uint32_t)g, (uint32_t)g << 12) : kNone;
         // Z covers the ranks k < span of this depth; merging Z with its copy
         // raised by span covers k < 2 span (|Q| is a power of two, so the
         // raised ranks never pass |Q| - 1)
         for (int span = d == 0 ? nq : 1; span < nq; span <<= 1) {
-            const bool ok = Zs < INF;
-            const int par = Zp & 0xfff;
-            const int k1 = ((Zp >> 12) & 63) + span;
-            const double Bs = ok ? cand_score_r(sh.scA[ok ? par : 0], w, k1) : INF;
-            const uint32_t Bp = ok ? Zp + ((uint32_t)span << 12) : kSentinel;
-            double ls;
-            uint32_t lp;
-            double cs[E];
-            uint32_t cp[E];
+            const bool ok = Z != kNone;
+            const uint32_t zp = key_packed(Z);
+            const uint32_t k1 = ((zp >> 12) & 63) + (uint32_t)span;
+            const uint64_t B = ok ? pkey(sh.scA[ok ? (zp & 0xfff) : 0] + c * k1, zp + ((uint32_t)span << 12)) : kNone;
+            uint64_t l, m;
             if constexpr (E == 1) {
-                ls = lane_read(Zs, K - 1);
-                lp = lane_read(Zp, K - 1);
-                cs[0] = lane_mirror(Bs);  // entry 63 - g of B
-                cp[0] = lane_mirror(Bp);
-                const bool tb = key_lt(cs[0], cp[0], Zs, Zp);
-                cs[0] = tb ? cs[0] : Zs;
-                cp[0] = tb ? cp[0] : Zp;
+                l = lane_read(Z, K - 1);
+                const uint64_t r = lane_mirror(B);  // entry 63 - g of B
+                m = r < Z ? r : Z;
             } else {
                 buf ^= 1;
-                sh.xs[buf][1][g] = Bs;
-                sh.xp[buf][1][g] = Bp;
-                if (g == K - 1) {
-                    sh.bcs[buf] = Zs;
-                    sh.bcp[buf] = Zp;
-                }
+                sh.xk[buf][1][g] = B;
+                if (g == K - 1)
+                    sh.bck[buf] = Z;
                 __syncthreads();
-                ls = sh.bcs[buf];
-                lp = sh.bcp[buf];
+                l = sh.bck[buf];
             }
             // stop when the cheapest entry with rank span can no longer
             // enter a full list (the same decision in every lane)
-            if (ls < INF) {
-                const double c0 = cand_score_r(a0s, w, span);
-                const uint32_t c0p = (a0p & 0xfffc0fffu) | ((uint32_t)span << 12);
-                if (!key_lt(c0, c0p, ls, lp))
-                    break;
-            }
+            if (l != kNone && !(pkey(a0s + c * (uint32_t)span, (a0p & 0xfffc0fffu) | ((uint32_t)span << 12)) < l))
+                break;
             if constexpr (E > 1) {
                 // half cleaner (entry g against entry KP - 1 - g of B), then
                 // the stages across wavefronts, one LDS exchange each
                 // (alternating buffers: one barrier per exchange)
                 {
-                    const double rs = sh.xs[buf][1][KP - 1 - g];
-                    const uint32_t rp = sh.xp[buf][1][KP - 1 - g];
-                    const bool tb = key_lt(rs, rp, Zs, Zp);
-                    cs[0] = tb ? rs : Zs;
-                    cp[0] = tb ? rp : Zp;
+                    const uint64_t r = sh.xk[buf][1][KP - 1 - g];
+                    m = r < Z ? r : Z;
                 }
 #pragma unroll
                 for (int js = E / 2; js >= 1; js >>= 1) {
                     buf ^= 1;
-                    sh.xs[buf][0][g] = cs[0];
-                    sh.xp[buf][0][g] = cp[0];
+                    sh.xk[buf][0][g] = m;
                     __syncthreads();
-                    const double os = sh.xs[buf][0][g ^ (64 * js)];
-                    const uint32_t op = sh.xp[buf][0][g ^ (64 * js)];
+                    const uint64_t o = sh.xk[buf][0][g ^ (64 * js)];
                     const bool lower = (g & (64 * js)) == 0;
-                    const bool take = lower == key_lt(os, op, cs[0], cp[0]);
-                    cs[0] = take ? os : cs[0];
-                    cp[0] = take ? op : cp[0];
+                    m = (lower == (o < m)) ? o : m;
                 }
             }
-            Zs = cs[0];
-            Zp = cp[0];
-            lane_stage<32>(Zs, Zp, true);
-            lane_stage<16>(Zs, Zp, true);
-            lane_stage<8>(Zs, Zp, true);
-            lane_stage<4>(Zs, Zp, true);
-            lane_stage<2>(Zs, Zp, true);
-            lane_stage<1>(Zs, Zp, true);
-            if (g >= K) {
-                Zs = INF;
-                Zp = kSentinel;
-            }
+            Z = m;
+            lane_stage<32>(Z, true);
+            lane_stage<16>(Z, true);
+            lane_stage<8>(Z, true);
+            lane_stage<4>(Z, true);
+            lane_stage<2>(Z, true);
+            lane_stage<1>(Z, true);
+            if (g >= K)
+                Z = kNone;
         }
         // lexical ranks of the new prefixes: the children of a parent are
         // k = 0..c-1, consecutive in lexical order.  cnt[] is zero here (set
         // at the start and cleared by its reader below).
-        if (Zs < INF)
-            atomicMax(&sh.cnt[Zp >> 18], ((Zp >> 12) & 63) + 1);
+        const uint32_t zp = key_packed(Z);
+        if (Z != kNone)
+            atomicMax(&sh.cnt[zp >> 18], ((zp >> 12) & 63) + 1);
         __syncthreads();
         {
             const uint32_t v = sh.cnt[g];
@@ -276,26 +231,24 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
             sh.run[g] = incl - v;  // exclusive prefix inside the wavefront
         }
         __syncthreads();
-        if (Zs < INF) {
-            const uint32_t k = (Zp >> 12) & 63;
-            const uint32_t pr = Zp >> 18;  // parent's lexical rank
+        if (Z != kNone) {
+            const uint32_t k = (zp >> 12) & 63;
+            const uint32_t pr = zp >> 18;  // parent's lexical rank
             uint32_t base = 0;
 #pragma unroll
             for (int j = 0; j < E - 1; ++j)
                 base += (uint32_t)j < (pr >> 6) ? sh.wsum[j] : 0u;
             const uint32_t lx = sh.run[pr] + base + k;
-            rec[(size_t)d * KP + g] = (uint16_t)((Zp & 0xffu) | (k << 8));  // parent position < 256
-            As = Zs;
-            Ap = (uint32_t)g | (lx << 18);
+            rec[(size_t)d * KP + g] = (uint16_t)((zp & 0xffu) | (k << 8));  // parent position < 256
+            Ak = pkey(key_cost(Z), (uint32_t)g | (lx << 18));
         } else {
-            As = INF;
-            Ap = kSentinel;
+            Ak = kNone;
         }
-        sh.scA[g] = As;
+        sh.scA[g] = key_cost(Ak);
         if (g == 0)
-            sh.ap0 = Ap;
+            sh.ap0 = key_packed(Ak);
         if (g == K - 1)
-            sh.apK1 = Ap;
+            sh.akK1 = Ak;
         __syncthreads();
     }
 
@@ -303,8 +256,7 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
     // note for each which depths ask for a rank >= 3 and >= 2
     const int nw = a.NP >> 2;
     const int r = g;
-    double ks = INF;
-    uint32_t kr = (uint32_t)r << 12;
+    uint64_t ks = kNone;  // sort key of path r; paths past K sort last
     if (r < K) {
         uint32_t wvd[kMaxN / 4];
 #pragma unroll
@@ -334,14 +286,15 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
         // whole wavefronts), the first depths with a rank >= 3 and >= 5 (the
         // costly point choices start together), then folds of the depths
         // with rank >= 3 and >= 2 (the key only groups paths; any order is
-        // correct).  Fields: 6 + 6 + 6 + 20 + 15 bits, exact in a double.
+        // correct), then the path itself.  Fields: 6 + 6 + 6 + 20 + 15 + 8
+        // bits.
         const uint32_t fd = m2 ? (uint32_t)__builtin_ctz(m2) : (uint32_t)N;
         const uint32_t f3 = m3 ? (uint32_t)__builtin_ctz(m3) : (uint32_t)N;
         const uint32_t f5 = m5 ? (uint32_t)__builtin_ctz(m5) : (uint32_t)N;
         const uint32_t m3f = (m3 ^ (m3 >> 20)) & 0xfffffu;
         const uint32_t m2f = (m2 ^ (m2 >> 15) ^ (m2 >> 30)) & 0x7fffu;
-        ks = (double)fd * 140737488355328.0 + (double)f3 * 2199023255552.0 + (double)f5 * 34359738368.0 +
-             (double)m3f * 32768.0 + (double)m2f;  // 2^47, 2^41, 2^35, 2^15
+        ks = ((uint64_t)fd << 55) | ((uint64_t)f3 << 49) | ((uint64_t)f5 << 43) | ((uint64_t)m3f << 23) |
+             ((uint64_t)m2f << 8) | (uint64_t)r;
     }
     // Lane order: paths sorted by that key, so that the lanes of one
     // wavefront leave path 0 at about the same depth and need the costly
@@ -355,23 +308,19 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
 #pragma unroll
             for (int stride = size / 2; stride >= 1; stride >>= 1) {
                 if (stride >= 64) {
-                    sh.xs[buf][0][g] = ks;
-                    sh.xp[buf][0][g] = kr;
+                    sh.xk[buf][0][g] = ks;
                     __syncthreads();
-                    const double os = sh.xs[buf][0][g ^ stride];
-                    const uint32_t op = sh.xp[buf][0][g ^ stride];
+                    const uint64_t o = sh.xk[buf][0][g ^ stride];
                     buf ^= 1;
                     const bool lower = (g & stride) == 0;
-                    const bool take = (lower == asc) == key_lt(os, op, ks, kr);
-                    ks = take ? os : ks;
-                    kr = take ? op : kr;
+                    ks = ((lower == asc) == (o < ks)) ? o : ks;
                 } else {
-                    lane_stage_n(ks, kr, stride, asc);
+                    lane_stage_n(ks, stride, asc);
                 }
             }
         }
         if (g < K)
-            a.order[(size_t)s * K + g] = (uint16_t)(kr >> 12);
+            a.order[(size_t)s * K + g] = (uint16_t)(ks & 0xffu);
     }
 }
 

@@ -240,31 +240,23 @@ __global__ __launch_bounds__(64) void sqrd_batch_kernel(const StageJob *jobs, in
 
 // ============================================================================
 // a2: position-vector set.
-// The score of a position vector is sum_d w_d (p_d - 1), accumulated in depth
-// order in float64 exactly as written (product, then sum; no contraction).
-// Depth by depth, the list of the K cheapest prefixes (in (score, lexical)
-// order) is extended: candidates are (prefix i, k) with score
-// sc_i + w_d * k, k = 0..|Q|-1.  Because every copy "list + k w_d" is a
+// The cost of a position vector is sum_d c_d (p_d - 1) in exact integers
+// (cost_unit: the depth weights scaled to 2^kCostBits of the largest and
+// rounded).  Depth by depth, the list of the K cheapest prefixes (in (cost,
+// lexical) order) is extended: candidates are (prefix i, k) with cost
+// sc_i + c_d k, k = 0..|Q|-1.  Because every copy "list + k c_d" is a
 // shifted copy of the sorted list, the top-K of their union is built as
 //     Z_0 = list,  Z_m = topK(list  U  shift(Z_{m-1})),
 // stopping when the cheapest entry with p_d = m+1 can no longer enter.
-// Each merge is a merge-path over two sorted lists in LDS.  Ties in score are
+// Each merge is a merge-path over two sorted lists in LDS.  Ties in cost are
 // ordered by the lexical rank of the parent prefix, then k, which is the
 // lexicographic order of the extended prefixes.  Back pointers
 // (parent, k) per depth rebuild the vectors at the end.
 // ============================================================================
 
-__device__ __forceinline__ bool key_less(double sa, int la, int ka, double sb, int lb, int kb)
+__device__ __forceinline__ bool key_less(uint32_t sa, int la, int ka, uint32_t sb, int lb, int kb)
 {
     return sa < sb || (sa == sb && (la < lb || (la == lb && ka < kb)));
-}
-
-// parent + w k with the product and the sum rounded separately (no fused
-// multiply-add), the rounding of a score summed term by term in depth order
-__device__ __forceinline__ double cand_score(double parent, double w, int k)
-{
-#pragma clang fp contract(off)
-    return parent + w * (double)k;
 }
 
 template <bool REC_LDS>
@@ -275,8 +267,8 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
     const int lane = threadIdx.x;
     const int s = blockIdx.x;
 
-    double *A_sc = (double *)smem;
-    double *Zs[2] = {A_sc + K, A_sc + 2 * K};
+    uint32_t *A_sc = (uint32_t *)smem;
+    uint32_t *Zs[2] = {A_sc + K, A_sc + 2 * K};
     uint16_t *A_lx = (uint16_t *)(A_sc + 3 * K);
     uint16_t *Zp[2] = {A_lx + K, A_lx + 2 * K};
     uint16_t *Zk[2] = {A_lx + 3 * K, A_lx + 4 * K};
@@ -284,14 +276,17 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
     uint32_t *rec = REC_LDS ? (cnt + K) : (a.rec_g + (size_t)s * N * K);
 
     if (lane == 0) {
-        A_sc[0] = 0.0;
+        A_sc[0] = 0u;
         A_lx[0] = 0;
     }
     int n = 1;
+    double wmax = 0.0;
+    for (int d = 0; d < N; ++d)
+        wmax = fmax(wmax, a.w[(size_t)s * N + d]);
     __syncthreads();
 
     for (int d = 0; d < N; ++d) {
-        const double wd = a.w[(size_t)s * N + d];
+        const uint32_t cd = cost_unit(a.w[(size_t)s * N + d], wmax);
         int cur = 0;
         for (int i = lane; i < n; i += 64) {
             Zs[0][i] = A_sc[i];
@@ -302,7 +297,7 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
         __syncthreads();
         for (int m = 1; m < nq; ++m) {
             if (zn == K) {
-                const double nm = cand_score(A_sc[0], wd, m);
+                const uint32_t nm = A_sc[0] + cd * (uint32_t)m;
                 const int zp = Zp[cur][K - 1];
                 if (!key_less(nm, A_lx[0], m, Zs[cur][K - 1], A_lx[zp], Zk[cur][K - 1]))
                     break;
@@ -313,7 +308,6 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
             const int chunk = (total + 63) / 64;
             const int p0 = min(total, lane * chunk);
             const int p1 = min(total, p0 + chunk);
-            const double *zs = Zs[cur];
             const uint16_t *zp = Zp[cur];
             const uint16_t *zk = Zk[cur];
             if (p0 < p1) {
@@ -323,7 +317,7 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
                     const int j = p0 - mid - 1;
                     const int par = zp[j];
                     const int kb = zk[j] + 1;
-                    const double sb = cand_score(A_sc[par], wd, kb);
+                    const uint32_t sb = A_sc[par] + cd * (uint32_t)kb;
                     if (key_less(A_sc[mid], A_lx[mid], 0, sb, A_lx[par], kb))
                         lo = mid + 1;
                     else
@@ -332,12 +326,12 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
                 int i = lo, j = p0 - lo;
                 for (int p = p0; p < p1; ++p) {
                     bool takeA;
-                    double sb = 0.0;
+                    uint32_t sb = 0u;
                     int par = 0, kb = 0;
                     if (j < zn) {
                         par = zp[j];
                         kb = zk[j] + 1;
-                        sb = cand_score(A_sc[par], wd, kb);
+                        sb = A_sc[par] + cd * (uint32_t)kb;
                     }
                     if (i >= n)
                         takeA = false;
@@ -631,7 +625,7 @@ bool posvec_rec_fits_lds(int N, int K)
 
 size_t posvec_lds_bytes(int N, int K, bool rec_in_lds)
 {
-    size_t b = (size_t)K * 3 * sizeof(double);           // A_sc, Zs[2]
+    size_t b = (size_t)K * 3 * sizeof(uint32_t);         // A_sc, Zs[2]
     b += (size_t)((5 * K + 1) & ~1) * sizeof(uint16_t);  // A_lx, Zp[2], Zk[2]
     b += (size_t)K * sizeof(uint32_t);                    // cnt
     if (rec_in_lds)

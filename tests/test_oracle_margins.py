@@ -91,12 +91,26 @@ def np_sqrd(H):
     return Q, R, perm, margin
 
 
+def np_depth_costs(w_depth):
+    """Integer depth costs: each weight in units of 2^-20 of the largest,
+    rounded half to even (0 for a weight that is not a number, or when the
+    largest is not positive and finite)."""
+    w = np.asarray(w_depth, np.float64)
+    wmax = max([0.0] + [x for x in w.tolist() if x > 0.0])
+    if not (0.0 < wmax < np.inf):
+        return np.zeros_like(w)
+    with np.errstate(invalid="ignore"):
+        x = (w / wmax) * float(1 << 20)
+        ok = (x >= 0.0) & (x <= float(1 << 20))
+    return np.where(ok, np.rint(np.where(ok, x, 0.0)), 0.0)
+
+
 def np_position_set(w_depth, nq, K):
-    """All |Q|^N vectors (depth order, entries 1..nq), sorted by score then
-    lexicographically; -> (first K vectors, boundary margin)."""
+    """All |Q|^N vectors (depth order, entries 1..nq), sorted by integer cost
+    then lexicographically; -> (first K vectors, boundary margin)."""
     N = len(w_depth)
     P = np.array(list(itertools.product(range(1, nq + 1), repeat=N)), dtype=np.int64)
-    score = (P - 1).astype(np.float64) @ np.asarray(w_depth, np.float64)
+    score = ((P - 1) @ np_depth_costs(w_depth).astype(np.int64)).astype(np.float64)
     keys = [P[:, d] for d in range(N - 1, -1, -1)] + [score]
     order = np.lexsort(keys)
     P, score = P[order], score[order]

@@ -124,6 +124,24 @@ def test_position_set_ties_are_lexicographic(w):
     assert keys == sorted(keys)
 
 
+@pytest.mark.parametrize("w,c1", [([1.0, 2.5 * 2.0 ** -20], 2),    # 2.5 units: half to even, down
+                                   ([1.0, 3.5 * 2.0 ** -20], 4),    # 3.5 units: half to even, up
+                                   ([4.0, 1.0], 2 ** 18),           # a quarter of the largest
+                                   ([2.0, float("nan")], 0),        # not a number: cost 0
+                                   ([0.0, 0.0], 0)])                # no positive weight: all 0
+def test_position_set_integer_depth_costs(w, c1):
+    """The scores are sums of integer depth costs: the weights in units of
+    2^-20 of the largest, rounded half to even.  With two depths the second
+    vector of the set is (1, 2), whose score is the cost of depth 1."""
+    P, sc, _ = oracle.position_set(np.array(w), 4, 3)
+    c0 = 2 ** 20 if max([x for x in w if x == x]) > 0 else 0
+    if c1 > 0:
+        assert P[:2].tolist() == [[1, 1], [1, 2]] and sc[1] == c1
+    assert sc[0] == 0
+    # every score is the integer combination sum_d c_d (p_d - 1)
+    assert np.array_equal(sc, (P.astype(np.int64) - 1) @ np.array([c0, c1]))
+
+
 def test_position_set_nested_and_clamped():
     w = np.array([0.3, 1.7, 0.9, 2.2])
     P64, _, _ = oracle.position_set(w, 4, 64)
@@ -472,9 +490,11 @@ def test_worked_example_diagonal_2x2_qpsk():
 
     H = diag(2, 1): SQRD takes the weaker column first, so perm = [1, 0],
     R = diag(1, 2) and depth 0 detects user 0 (R_11 = 2), depth 1 user 1.
-    Depth weights are (4, 1), so the four cheapest position vectors are
-    (1,1), (1,2), (1,3), (1,4) with scores 0, 1, 2, 3: every path keeps user
-    0 at its nearest point and walks user 1 through its 1st..4th nearest.
+    Depth weights are (4, 1), integer depth costs (2^20, 2^18) (the weights
+    in units of 2^-20 of the largest), so the four cheapest position vectors
+    are (1,1), (1,2), (1,3), (1,4) with scores 0, 1, 2, 3 times 2^18: every
+    path keeps user 0 at its nearest point and walks user 1 through its
+    1st..4th nearest.
     QPSK points: index 0 = (-D,-D), 1 = (-D,+D), 2 = (+D,-D), 3 = (+D,+D),
     D = 1/sqrt(2).  With y = (1 + 0.3j, -0.2 + 0.9j):
       user 0: z = y0 / 2 = 0.5 + 0.15j, nearest is index 3;
@@ -491,7 +511,7 @@ def test_worked_example_diagonal_2x2_qpsk():
     assert np.allclose(w, [4, 1])
     P, sc, _ = oracle.position_set(w, 4, 4)
     assert P.tolist() == [[1, 1], [1, 2], [1, 3], [1, 4]]
-    assert np.allclose(sc, [0, 1, 2, 3])
+    assert sc.tolist() == [0, 2 ** 18, 2 * 2 ** 18, 3 * 2 ** 18]
     r = oracle.mpnl_vector(Q, R, perm, P, y, 2)
     assert r["paths"][:, 0].tolist() == [3, 3, 3, 3]
     assert r["paths"][:, 1].tolist() == [1, 3, 0, 2]
