@@ -388,8 +388,8 @@ def run_cells(args) -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    plan = ctx.batch_plan([dict(S=c.S, T=T, M=c.M, N=c.N, mod=c.bits, n_paths=c.n_paths) for c in cells],
-                          autotune=not args.no_autotune)
+    shapes = [dict(S=c.S, T=T, M=c.M, N=c.N, mod=c.bits, n_paths=c.n_paths) for c in cells]
+    plan = ctx.batch_plan(shapes, autotune=not args.no_autotune)
     stream = torch.cuda.current_stream()
     for _ in range(max(args.warmup, 1)):
         plan.run(jobs)
@@ -416,27 +416,6 @@ def run_cells(args) -> int:
     torch.cuda.synchronize()
     step_ms = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
 
-    # stage split of the same launches, enqueued one by one with the
-    # library's timers (HIP events on the launch stream around every kernel)
-    ctx.profile(True)
-    ctx.profile_collect()
-    n_prof = 5
-    for _ in range(n_prof):
-        plan.run(jobs)
-    torch.cuda.synchronize()
-    prof = ctx.profile_collect()
-    ctx.profile(False)
-    stages = {k: round(v[0] / n_prof, 5) for k, v in prof.items()}
-    paths_ms, paths_n = prof["paths"]
-    flops_cells = [c.S * T * path_flops_per_vector(c.N, K) for c, K in zip(cells, Ks)]
-    flops_run = sum(flops_cells)
-    # the path launches run side by side on graph branches: the device time
-    # of the path stage is its window on the batch's stream, not the sum of
-    # the launch durations (which counts overlapped time once per launch)
-    path_ms_step = prof["path_window"][0] / n_prof
-    launch_sum_ms_step = (paths_ms + prof["bound"][0]) / n_prof
-    achieved = flops_run / (path_ms_step * 1e-3) / 1e12
-
     # end to end with the PCIe copies: H and y from pinned host memory, the
     # decisions back to pinned host memory, one batch per step
     host_in = [(j["H"].cpu().pin_memory(), j["y"].cpu().pin_memory()) for j in jobs]
@@ -456,6 +435,43 @@ def run_cells(args) -> int:
     pcie_bytes = sum(hh.numel() * 8 + hy.numel() * 8 for hh, hy in host_in) + sum(o.numel() * 4 for o in host_out)
     plan_shapes_cache = plan.launch_shapes()
     plan.close()
+
+    # stage split, enqueued launch by launch with the library's timers (HIP
+    # events on the launch stream around every kernel), on a plan of the same
+    # jobs in one pipeline phase: in the timed plan the channel steps of the
+    # second phase run beside the path searches of the first, so a window of
+    # its path stage would hold them too.  Its throughput is reported beside.
+    # The timed plan is closed first: its graph branches' streams would share
+    # the device's hardware queues with this plan's.
+    splan = ctx.batch_plan(shapes, autotune=not args.no_autotune, serial=True)
+    for _ in range(max(args.warmup, 1)):
+        splan.run(jobs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        splan.run(jobs)
+    torch.cuda.synchronize()
+    serial_value = nvec * args.steps / (time.perf_counter() - t0)
+    ctx.profile(True)
+    ctx.profile_collect()
+    n_prof = 5
+    for _ in range(n_prof):
+        splan.run(jobs)
+    torch.cuda.synchronize()
+    prof = ctx.profile_collect()
+    ctx.profile(False)
+    splan.close()
+    stages = {k: round(v[0] / n_prof, 5) for k, v in prof.items()}
+    paths_ms, paths_n = prof["paths"]
+    flops_cells = [c.S * T * path_flops_per_vector(c.N, K) for c, K in zip(cells, Ks)]
+    flops_run = sum(flops_cells)
+    # the path launches run side by side on graph branches: the device time
+    # of the path stage is its window on the batch's stream, not the sum of
+    # the launch durations (which counts overlapped time once per launch)
+    path_ms_step = prof["path_window"][0] / n_prof
+    launch_sum_ms_step = (paths_ms + prof["bound"][0]) / n_prof
+    achieved = flops_run / (path_ms_step * 1e-3) / 1e12
+
 
     # per-job latency: each cell-slot detected alone (a1..a5, one detect
     # call), in the batch's precision and in plain FP32, events around each
@@ -531,7 +547,8 @@ def run_cells(args) -> int:
             "achieved_is": "algorithmic flops of all N_p paths per batch / wall time of the path stage per "
                            "batch (HIP events on the batch's stream from the first bound launch to the join of "
                            "the graph branches that carry the path-search launches, their group reductions "
-                           "and bounds); an effective rate, pruning skips work",
+                           "and bounds, in the same batch planned in one pipeline phase); an effective rate, "
+                           "pruning skips work",
             "flops_per_step": flops_run, "path_ms_per_step": path_ms_step,
             "path_launch_ms_sum_per_step": launch_sum_ms_step,
             "path_launches_per_step": paths_n / n_prof}
@@ -549,11 +566,12 @@ def run_cells(args) -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[prec], "data": "synthetic",
         "config": {"workload": CELLS_WORKLOAD, "cells": len(cells), "symbols": T, "snr_db": snr,
                    "precision": prec, "channel": "iid", "vectors_per_step": nvec,
-                   "form": "planned batch (graph replay)",
+                   "form": "planned batch (graph replay, two pipeline phases)",
                    "shapes": [[c.N, c.M, c.bits, c.S, K] for c, K in zip(cells, Ks)],
                    "autotune": not args.no_autotune},
         "p50_step_ms": float(np.percentile(step_ms, 50)),
         "p99_step_ms": float(np.percentile(step_ms, 99)),
+        "serial_plan_vectors_per_s": serial_value,
         "plain_fp32_per_cell_vectors_per_s": plain,
         "speedup_vs_plain_fp32": value / plain,
         "detected_mbit_per_s": value * sum(c.S * c.N * c.bits for c in cells) / sum(c.S for c in cells) / 1e6,

@@ -322,6 +322,12 @@ typedef struct mpnl_batch mpnl_batch;
                                    without it every launch runs
                                    one-wavefront groups, group major, four
                                    per workgroup                            */
+#define MPNL_BATCH_SERIAL 2u    /* one pipeline phase: every path search
+                                   after every channel step (a1 .. a3);
+                                   without it the jobs split into two
+                                   phases by path-search work and the
+                                   channel steps of the second run beside
+                                   the path searches of the first          */
 
 /* Pooled processing as mpnl_detect_batch() (Sec. II-A) for a set of cells
    whose shapes repeat from slot to slot.  Plan an uneven multi-cell batch
@@ -330,7 +336,9 @@ typedef struct mpnl_batch mpnl_batch;
    slot state and workspace once from the context budget and groups the jobs
    into batched launches: sorted QR per antenna-count bucket, position sets
    per path-count bucket, one rotation launch, and one path-search launch per
-   (user count, modulation, workgroup size).  The first
+   (user count, modulation, workgroup size), all of these per pipeline phase
+   (MPNL_BATCH_SERIAL); the path searches run on three graph branches,
+   balanced by their work.  The first
    mpnl_batch_run() captures the sequence (job-table upload + launches) into
    HIP graphs that later runs replay.  Every job needs n_paths clamped to
    <= 256.  Errors: as mpnl_detect() for any job, MPNL_E_UNSUPPORTED for more

@@ -44,6 +44,7 @@ EXPORTED = (
 MPNL_JOB_DONE, MPNL_JOB_REJECTED, MPNL_JOB_DROPPED, MPNL_JOB_FAILED = 0, 1, 2, 3
 MPNL_CREATE_NO_PRUNE = 1
 MPNL_BATCH_AUTOTUNE = 1
+MPNL_BATCH_SERIAL = 2
 MPNL_STAGE_SQRD, MPNL_STAGE_POSVEC, MPNL_STAGE_ROTATE, MPNL_STAGE_PATHS, MPNL_STAGE_BOUND = 0, 1, 2, 3, 4
 MPNL_STAGE_PATH_WINDOW = 5
 STAGE_NAMES = ("sqrd", "posvec", "rotate", "paths", "bound", "path_window")
@@ -466,8 +467,8 @@ class Context:
         mpnl_detect_batch(self.handle, jobs, stream)
         return [j["out"] for j in jobs]
 
-    def batch_plan(self, shapes: Sequence[dict], autotune: bool = False) -> "BatchPlan":
-        return BatchPlan(self, shapes, autotune)
+    def batch_plan(self, shapes: Sequence[dict], autotune: bool = False, serial: bool = False) -> "BatchPlan":
+        return BatchPlan(self, shapes, autotune, serial)
 
 
 class BatchPlan:
@@ -475,10 +476,11 @@ class BatchPlan:
     job) replays as one captured graph; each run takes new tensors of the
     same shapes."""
 
-    def __init__(self, ctx: Context, shapes: Sequence[dict], autotune: bool = False):
+    def __init__(self, ctx: Context, shapes: Sequence[dict], autotune: bool = False, serial: bool = False):
         self.ctx = ctx
         self.shapes = [dict(s) for s in shapes]
-        self.handle = mpnl_batch_create(ctx.handle, self.shapes, MPNL_BATCH_AUTOTUNE if autotune else 0)
+        flags = (MPNL_BATCH_AUTOTUNE if autotune else 0) | (MPNL_BATCH_SERIAL if serial else 0)
+        self.handle = mpnl_batch_create(ctx.handle, self.shapes, flags)
 
     def run(self, jobs: Sequence[dict], stream=None):
         mpnl_batch_run(self.ctx.handle, self.handle, jobs, stream)

@@ -980,6 +980,7 @@ struct PlanLaunch {
     int vpw;          // a4: work items (vector, path group) per workgroup (tuned)
     int gmajor;       // a4: 1 = work items numbered path group major (tuned)
     int branch;       // a4: graph branch of the launch (plan_branches)
+    int phase;        // pipeline phase of the launch (plan_layout)
     double gflop;     // a4: path-search work of the launch (algorithmic)
     int bound_items;  // a4: items of the pruning-bound launch
     int items;
@@ -989,8 +990,14 @@ struct PlanLaunch {
 
 constexpr int kGraphCopies = 2;
 // branches of the planned batch's path-search launches
-constexpr int kMaxBranches = 4;
+constexpr int kMaxBranches = 4;  // side streams: kMaxBranches - 1
 constexpr int kPlanBranches = 3;
+static_assert(kPlanBranches < kMaxBranches, "a phased plan needs a side stream per branch");
+// pipeline phases of a planned batch (plan_layout), unless MPNL_BATCH_SERIAL.
+// 40 cells FP16: one phase 148.5, two 152.6, three 146.5 M vectors/s (FP32:
+// 137.6, 139.4, 136.8)
+constexpr int kMaxPhases = 4;
+constexpr int kPlanPhases = 2;
 
 // Byte offsets of one job's arrays in a batch's block.
 struct PlanJobOffsets {
@@ -1026,8 +1033,9 @@ struct mpnl_batch {
     // (see plan_enqueue): the other branches' streams, the fork event and
     // their join events
     int branches = 1;
+    int phases = 1;
     hipStream_t side[kMaxBranches - 1] = {};
-    hipEvent_t fork_ev = nullptr;
+    hipEvent_t fork_ev[kMaxPhases] = {};
     hipEvent_t join_ev[kMaxBranches - 1] = {};
 };
 
@@ -1036,16 +1044,28 @@ namespace {
 // Device-memory layout and launch groups of a batch of job shapes (every
 // job with n_paths clamped to <= 256): per job its slot state, rotated
 // vectors, pruning record and path-group partials, then the job tables.
-// Fills p->launches, p->table_bytes and the per-job offsets; returns the
-// bytes before the tables (each table copy takes p->table_bytes more).
-size_t plan_layout(mpnl_batch *p, bool prune)
+// With phases > 1 the jobs are split into pipeline phases (whole path-search
+// groups, largest algorithmic work first, each to the phase with the least
+// work so far), each phase with its own a1 .. a3 launches, so that the
+// channel steps of one phase can run beside the path searches of the one
+// before.  Fills p->launches (phase by phase, stage by stage),
+// p->table_bytes and the per-job offsets; returns the bytes before the
+// tables (each table copy takes p->table_bytes more).
+size_t plan_layout(mpnl_batch *p, bool prune, int phases = 1)
 {
     const int n_jobs = (int)p->shapes.size();
     p->off.assign(n_jobs, PlanJobOffsets{});
     size_t total = 0;
+    auto clamped_paths = [](const mpnl_job &j) {
+        return (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
+    };
+    auto path_gflop = [&](const mpnl_job &j) {
+        const int K = clamped_paths(j);
+        return (double)j.S * j.T * K * (4.0 * j.N * (j.N - 1) + 11.0 * j.N) * 1e-9;
+    };
     for (int i = 0; i < n_jobs; ++i) {
         const mpnl_job &j = p->shapes[i];
-        const int K = (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
+        const int K = clamped_paths(j);
         PlanJobOffsets &o = p->off[i];
         o.lay = slot_layout(j.S, j.M, j.N, K, (j.N + 3) / 4 * 4, false);
         o.base = total;
@@ -1058,13 +1078,52 @@ size_t plan_layout(mpnl_batch *p, bool prune)
         o.part = total;
         total += align_up(mpnl::multi_partial_bytes(j.S, j.T, j.N, K));
     }
+    // phase of every job: that of its path-search group (N, constellation,
+    // lanes), groups spread over the phases by work
+    phases = std::max(1, std::min(phases, kMaxPhases));
+    std::vector<int> job_phase(n_jobs, 0);
+    if (phases > 1) {
+        struct PathKey {
+            int N, mod, lanes;
+            double gflop;
+            int phase;
+        };
+        std::vector<PathKey> keys;
+        std::vector<int> job_key(n_jobs);
+        for (int i = 0; i < n_jobs; ++i) {
+            const mpnl_job &j = p->shapes[i];
+            const int lanes = (clamped_paths(j) + 63) / 64 * 64;
+            int k = 0;
+            while (k < (int)keys.size() && !(keys[k].N == j.N && keys[k].mod == j.mod && keys[k].lanes == lanes))
+                ++k;
+            if (k == (int)keys.size())
+                keys.push_back(PathKey{j.N, j.mod, lanes, 0.0, 0});
+            keys[k].gflop += path_gflop(j);
+            job_key[i] = k;
+        }
+        std::vector<int> by_work(keys.size());
+        for (size_t k = 0; k < keys.size(); ++k)
+            by_work[k] = (int)k;
+        std::stable_sort(by_work.begin(), by_work.end(),
+                         [&](int a, int b) { return keys[a].gflop > keys[b].gflop; });
+        std::vector<double> load(phases, 0.0);
+        for (int k : by_work) {
+            const int ph = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            keys[k].phase = ph;
+            load[ph] += keys[k].gflop;
+        }
+        for (int i = 0; i < n_jobs; ++i)
+            job_phase[i] = keys[job_key[i]].phase;
+    }
+    p->phases = phases;
     // launch groups
     p->launches.clear();
-    auto group = [&](int kind, int param, int bits, int threads) -> PlanLaunch & {
+    auto group = [&](int phase, int kind, int param, int bits, int threads) -> PlanLaunch & {
         for (PlanLaunch &L : p->launches)
-            if (L.kind == kind && L.param == param && L.bits == bits && L.threads == threads)
+            if (L.phase == phase && L.kind == kind && L.param == param && L.bits == bits && L.threads == threads)
                 return L;
         PlanLaunch L{};
+        L.phase = phase;
         L.kind = kind;
         L.param = param;
         L.bits = bits;
@@ -1075,29 +1134,32 @@ size_t plan_layout(mpnl_batch *p, bool prune)
         p->launches.push_back(L);
         return p->launches.back();
     };
-    for (int stage = 0; stage < 4; ++stage)
-        for (int i = 0; i < n_jobs; ++i) {
-            const mpnl_job &j = p->shapes[i];
-            const int K = (int)std::min<long long>(j.n_paths, num_vectors_sat(1 << j.mod, j.N));
-            PlanLaunch *L;
-            if (stage == L_SQRD) {
-                L = &group(L_SQRD, (j.M + 3) / 4 * 4, 0, 64);
-                L->items += (j.S + 1) / 2;
-            } else if (stage == L_POSVEC) {
-                L = &group(L_POSVEC, K <= 64 ? 1 : K <= 128 ? 2 : 4, 0, 64);
-                L->items += j.S;
-                L->nmax = std::max(L->nmax, j.N);
-            } else if (stage == L_ROTATE) {
-                L = &group(L_ROTATE, 0, 0, 64);
-                L->items += j.S;
-            } else {
-                L = &group(L_PATHS, j.N, j.mod, (K + 63) / 64 * 64);
-                L->items += j.S * j.T;
-                L->bound_items += (j.S * j.T + 63) / 64;
-                L->gflop += (double)j.S * j.T * K * (4.0 * j.N * (j.N - 1) + 11.0 * j.N) * 1e-9;
+    for (int phase = 0; phase < phases; ++phase)
+        for (int stage = 0; stage < 4; ++stage)
+            for (int i = 0; i < n_jobs; ++i) {
+                if (job_phase[i] != phase)
+                    continue;
+                const mpnl_job &j = p->shapes[i];
+                const int K = clamped_paths(j);
+                PlanLaunch *L;
+                if (stage == L_SQRD) {
+                    L = &group(phase, L_SQRD, (j.M + 3) / 4 * 4, 0, 64);
+                    L->items += (j.S + 1) / 2;
+                } else if (stage == L_POSVEC) {
+                    L = &group(phase, L_POSVEC, K <= 64 ? 1 : K <= 128 ? 2 : 4, 0, 64);
+                    L->items += j.S;
+                    L->nmax = std::max(L->nmax, j.N);
+                } else if (stage == L_ROTATE) {
+                    L = &group(phase, L_ROTATE, 0, 0, 64);
+                    L->items += j.S;
+                } else {
+                    L = &group(phase, L_PATHS, j.N, j.mod, (K + 63) / 64 * 64);
+                    L->items += j.S * j.T;
+                    L->bound_items += (j.S * j.T + 63) / 64;
+                    L->gflop += path_gflop(j);
+                }
+                L->jobs.push_back(i);
             }
-            L->jobs.push_back(i);
-        }
     p->table_bytes = 0;
     for (PlanLaunch &L : p->launches) {
         L.off = p->table_bytes;
@@ -1146,21 +1208,24 @@ void plan_bind(mpnl_batch *p, char *dbase)
     }
 }
 
-// Spread the path-search launches over `branches` graph branches: largest
-// algorithmic work first, each to the branch with the least work so far.
+// Spread the path-search launches of each phase over `branches` graph
+// branches: largest algorithmic work first, each to the branch with the
+// least work so far.
 void plan_branches(mpnl_batch *p, int branches)
 {
-    std::vector<PlanLaunch *> paths;
-    for (PlanLaunch &L : p->launches)
-        if (L.kind == L_PATHS)
-            paths.push_back(&L);
-    std::stable_sort(paths.begin(), paths.end(),
-                     [](const PlanLaunch *a, const PlanLaunch *b) { return a->gflop > b->gflop; });
-    std::vector<double> load(std::max(branches, 1), 0.0);
-    for (PlanLaunch *L : paths) {
-        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        L->branch = b;
-        load[b] += L->gflop;
+    for (int phase = 0; phase < p->phases; ++phase) {
+        std::vector<PlanLaunch *> paths;
+        for (PlanLaunch &L : p->launches)
+            if (L.kind == L_PATHS && L.phase == phase)
+                paths.push_back(&L);
+        std::stable_sort(paths.begin(), paths.end(),
+                         [](const PlanLaunch *a, const PlanLaunch *b) { return a->gflop > b->gflop; });
+        std::vector<double> load(std::max(branches, 1), 0.0);
+        for (PlanLaunch *L : paths) {
+            const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            L->branch = b;
+            load[b] += L->gflop;
+        }
     }
 }
 
@@ -1222,12 +1287,18 @@ hipError_t plan_enqueue(mpnl_batch *p, int b, hipStream_t st, mpnl_ctx *timed = 
 {
     hipError_t e = hipMemcpyAsync(p->dev_table[b], p->pinned[b], p->table_bytes, hipMemcpyHostToDevice, st);
     // With several branches the path-search launches (bound, search and
-    // reduction of one group stay together) go round-robin over `st` and
-    // the side streams after the rotation; the side streams join `st` again
-    // at the end: branches of the captured graph, so that the tail of one
+    // reduction of one group stay together) go to the branch streams after
+    // the rotation of their phase, and the side streams join `st` again at
+    // the end: branches of the captured graph, so that the tail of one
     // launch overlaps the next launches instead of leaving the device idle.
+    // With one phase the branches are `st` and the side streams; with
+    // several, the side streams only: `st` runs the a1 .. a3 launches of
+    // the next phase meanwhile.
     const bool fork = p->branches > 1;
+    const bool phased = p->phases > 1;
+    const int nside = phased ? p->branches : p->branches - 1;
     bool forked = false, in_paths = false;
+    int fork_phase = -1;
     const hipStream_t st0 = st;
     // the window of the path stage on `st`: first path launch to the join
     hipEvent_t win0 = nullptr, win1 = nullptr;
@@ -1247,16 +1318,17 @@ hipError_t plan_enqueue(mpnl_batch *p, int b, hipStream_t st, mpnl_ctx *timed = 
                 break;
         }
         if (fork && L.kind == L_PATHS) {
-            if (!forked) {
-                e = hipEventRecord(p->fork_ev, st0);
-                for (int k = 0; k + 1 < p->branches && e == hipSuccess; ++k)
-                    e = hipStreamWaitEvent(p->side[k], p->fork_ev, 0);
+            if (L.phase != fork_phase) {  // the first path launch of a phase
+                fork_phase = L.phase;
+                e = hipEventRecord(p->fork_ev[L.phase], st0);
+                for (int k = 0; k < nside && e == hipSuccess; ++k)
+                    e = hipStreamWaitEvent(p->side[k], p->fork_ev[L.phase], 0);
                 if (e != hipSuccess)
                     break;
                 forked = true;
             }
             const int br = L.branch % p->branches;
-            st = br ? p->side[br - 1] : st0;
+            st = phased ? p->side[br] : br ? p->side[br - 1] : st0;
         }
         char *tab = p->dev_table[b] + L.off;
         const int nj = (int)L.jobs.size();
@@ -1291,7 +1363,7 @@ hipError_t plan_enqueue(mpnl_batch *p, int b, hipStream_t st, mpnl_ctx *timed = 
             }
         }
     }
-    for (int k = 0; forked && k + 1 < p->branches && e == hipSuccess; ++k) {
+    for (int k = 0; forked && k < nside && e == hipSuccess; ++k) {
         e = hipEventRecord(p->join_ev[k], p->side[k]);
         if (e == hipSuccess)
             e = hipStreamWaitEvent(st0, p->join_ev[k], 0);
@@ -1415,8 +1487,9 @@ void plan_free(mpnl_ctx *ctx, mpnl_batch *p)
         if (p->join_ev[k])
             (void)hipEventDestroy(p->join_ev[k]);
     }
-    if (p->fork_ev)
-        (void)hipEventDestroy(p->fork_ev);
+    for (int k = 0; k < kMaxPhases; ++k)
+        if (p->fork_ev[k])
+            (void)hipEventDestroy(p->fork_ev[k]);
     if (p->block >= 0)
         pool_release(ctx, p->block, nullptr);
     delete p;
@@ -1524,7 +1597,7 @@ int mpnl_detect_batch(mpnl_ctx *ctx, const mpnl_job *jobs, int n_jobs, void *str
 
 int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigned flags, mpnl_batch **out)
 {
-    if (!ctx || !shapes || n_jobs <= 0 || !out || (flags & ~MPNL_BATCH_AUTOTUNE))
+    if (!ctx || !shapes || n_jobs <= 0 || !out || (flags & ~(MPNL_BATCH_AUTOTUNE | MPNL_BATCH_SERIAL)))
         return MPNL_E_INVAL;
     *out = nullptr;
     for (int i = 0; i < n_jobs; ++i) {
@@ -1550,7 +1623,7 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
     p->precision = ctx->precision;
     p->prune = ctx->prune;
 
-    const size_t tables_at = plan_layout(p, ctx->prune);
+    const size_t tables_at = plan_layout(p, ctx->prune, (flags & MPNL_BATCH_SERIAL) ? 1 : kPlanPhases);
     const size_t total = tables_at + kGraphCopies * p->table_bytes;
     int rc = pool_alloc(ctx, total, nullptr, &p->block);
     if (rc != MPNL_OK) {
@@ -1569,8 +1642,11 @@ int mpnl_batch_create(mpnl_ctx *ctx, const mpnl_job *shapes, int n_jobs, unsigne
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     if (e == hipSuccess && kPlanBranches > 1) {
-        e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
-        for (int k = 0; k + 1 < kPlanBranches && e == hipSuccess; ++k) {
+        for (int k = 0; k < p->phases && e == hipSuccess; ++k)
+            e = hipEventCreateWithFlags(&p->fork_ev[k], hipEventDisableTiming);
+        // one side stream per branch when the phases keep `st` for a1 .. a3
+        const int nside = p->phases > 1 ? kPlanBranches : kPlanBranches - 1;
+        for (int k = 0; k < nside && e == hipSuccess; ++k) {
             e = hipStreamCreateWithFlags(&p->side[k], hipStreamNonBlocking);
             if (e == hipSuccess)
                 e = hipEventCreateWithFlags(&p->join_ev[k], hipEventDisableTiming);

@@ -53,11 +53,14 @@ def _jobs(shapes, seed):
     return jobs, slots
 
 
-@pytest.mark.parametrize("autotune", [False, True])
-def test_plan_replays_equal_alone(ctx, autotune):
-    _say("batch plan replays, autotune", autotune)
+@pytest.mark.parametrize("autotune,serial", [(False, False), (True, False), (False, True)])
+def test_plan_replays_equal_alone(ctx, autotune, serial):
+    """Replays equal every job detected alone: with the default two pipeline
+    phases (the channel steps of the second beside the path searches of the
+    first) and with one (MPNL_BATCH_SERIAL)."""
+    _say("batch plan replays, autotune", autotune, "serial", serial)
     plan = ctx.batch_plan([dict(S=S, T=T, M=M, N=N, mod=b, n_paths=K) for S, T, M, N, b, K in SMALL],
-                          autotune=autotune)
+                          autotune=autotune, serial=serial)
     try:
         for rep in range(3):
             jobs, slots = _jobs(SMALL, 300 + rep)
