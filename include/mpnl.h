@@ -72,8 +72,7 @@ extern "C" {
 #define MPNL_QAM16 4
 #define MPNL_QAM64 6
 
-/* arithmetic of the path search (a4/a5); a1-a3 always run in float32 with
-   the pivot norms in float64 */
+/* arithmetic of the path search (a4/a5); a1-a3 always run in float32 */
 #define MPNL_PREC_FP32 0        /* float32 residuals and metric              */
 #define MPNL_PREC_FP16 1        /* float16 R / residual operands, float32
                                    accumulation of products and the metric  */
