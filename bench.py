@@ -160,6 +160,8 @@ def main() -> int:
     ap.add_argument("--rate", type=float, default=20000.0, help="serving: offered jobs/s")
     ap.add_argument("--jobs", type=int, default=2000, help="serving: jobs per run")
     ap.add_argument("--no-autotune", action="store_true", help="batch workload: default grid sizes")
+    ap.add_argument("--serial", action="store_true",
+                    help="batch workload: time the plan in one pipeline phase (as the stage split does)")
     ap.add_argument("--paths", type=int, default=0)
     ap.add_argument("--precision", default=None, choices=sorted(PRECISIONS),
                     help="path-metric arithmetic (default: fp16 for the 40-cell batch, else fp32)")
@@ -389,7 +391,7 @@ def run_cells(args) -> int:
         torch.cuda.synchronize()
         del src, dst
     shapes = [dict(S=c.S, T=T, M=c.M, N=c.N, mod=c.bits, n_paths=c.n_paths) for c in cells]
-    plan = ctx.batch_plan(shapes, autotune=not args.no_autotune)
+    plan = ctx.batch_plan(shapes, autotune=not args.no_autotune, serial=args.serial)
     stream = torch.cuda.current_stream()
     for _ in range(max(args.warmup, 1)):
         plan.run(jobs)
@@ -566,7 +568,8 @@ def run_cells(args) -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[prec], "data": "synthetic",
         "config": {"workload": CELLS_WORKLOAD, "cells": len(cells), "symbols": T, "snr_db": snr,
                    "precision": prec, "channel": "iid", "vectors_per_step": nvec,
-                   "form": "planned batch (graph replay, two pipeline phases)",
+                   "form": "planned batch (graph replay, %s)" % ("one pipeline phase" if args.serial
+                                                                  else "two pipeline phases"),
                    "shapes": [[c.N, c.M, c.bits, c.S, K] for c, K in zip(cells, Ks)],
                    "autotune": not args.no_autotune},
         "p50_step_ms": float(np.percentile(step_ms, 50)),
