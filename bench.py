@@ -89,14 +89,16 @@ def _counter_summary(name: str):
 
 
 def measured_traffic(workload: str, K: int, precision: str):
-    """HBM bytes per path-search launch from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, calibrated), only while the kernel's sources are
-    unchanged since the counters were taken; else None."""
+    """Counter figures of one path-search launch of the 16x16 slot from the
+    committed summary: HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated), VALU
+    and FP32 FMA wave-instructions and the traced kernel time, only while the
+    kernel's sources are unchanged since the counters were taken; else None."""
     if workload != "16x16-qam16-S1200-T14" or K != 256 or precision != "fp32":
         return None
     kv = _counter_summary("traffic_path_search_16x16-qam16-S1200-T14-Np256.txt")
     try:
-        return float(kv["traffic_bytes_per_launch"]) if kv else None
+        return {k: float(kv[k]) for k in ("traffic_bytes_per_launch", "valu_wave_insts_per_launch",
+                                          "fma_f32_wave_insts_per_launch", "trace_kernel_us")} if kv else None
     except (KeyError, ValueError):
         return None
 
@@ -284,9 +286,22 @@ def main() -> int:
         "stage_ms_per_launch": stages,
         "roofline": {"bound": "alu", "kernel": "path_search_kernel", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic(args.workload, Kc, args.precision),
+                     "traffic": None,
+                     "achieved_is": "algorithmic flops of all N_p paths per launch / path-search time per "
+                                    "launch (search + group reduction, HIP events on the launch stream); an "
+                                    "effective rate, pruning skips work",
                      "flops_per_launch": flops_launch, "avg_launch_ms": avg_paths_s * 1e3},
     }
+    cnt = measured_traffic(args.workload, Kc, args.precision)
+    if cnt:
+        roof = res["roofline"]
+        roof["traffic"] = cnt["traffic_bytes_per_launch"]
+        t_s = cnt["trace_kernel_us"] * 1e-6  # the traced search kernel alone
+        roof["valu_issue_frac"] = cnt["valu_wave_insts_per_launch"] / (VALU_ISSUE_PER_S * t_s)
+        roof["valu_issue_is"] = ("VALU wave64 instructions per launch (counters) / (256 CUs x 1 per cycle x "
+                                 "2.4 GHz x traced kernel time)")
+        roof["executed_fma_f32_tflops"] = cnt["fma_f32_wave_insts_per_launch"] * 128 / t_s / 1e12
+        roof["rocprof_kernel_us"] = cnt["trace_kernel_us"]
     if not args.no_cpu_baseline:
         n_sub = args.cpu_subcarriers or min(S, {4: 64, 16: 1200, 24: 1000}.get(N, 200))
         res["cpu_baseline"] = cpu_baseline(sl, bits, Kc, n_sub)
