@@ -371,8 +371,11 @@ int orc_sqrd(const cplx *H, int M, int N, cplx *Q, cplx *R, int32_t *perm,
 /* 2^-20, rounded to the nearest integer (ties to even); a weight that is  */
 /* not a number, or a largest weight that is not positive and finite,      */
 /* gives cost 0.  Sums of such integers are exact, so ties are exact ties. */
-/* The set is the first K = min(N_p, |Q|^N) vectors in (score ascending,   */
-/* p lexicographic ascending) order.                                        */
+/* The set is the first K = min(N_p, |Q|^N) vectors in ascending order of  */
+/* the key (C_N, C_{N-1}, ..., C_1, p_0, ..., p_{N-1}), C_j = the cost of  */
+/* the prefix of the first j depths (C_N = score): equal scores go by the   */
+/* cheaper longest prefix, then the next, and the same costs throughout by  */
+/* p lexicographically.                                                     */
 /*                                                                          */
 /* Best-first search: pop the smallest vector, emit it, push its canonical  */
 /* children p + e_j for every j >= last(p) with p_j < |Q|, where last(p) is */
@@ -409,20 +412,28 @@ static double pv_score(const double *c, const uint8_t *p, int N)
     return s;
 }
 
-static int pv_before(const pv_entry *a, const pv_entry *b, int N)
+static int pv_before(const pv_entry *a, const pv_entry *b, int N, const double *c)
 {
     if (a->score != b->score)
         return a->score < b->score;
+    /* equal scores: prefix costs C_{N-1} .. C_1 (exact integer arithmetic) */
+    double pa = a->score, pb = b->score;
+    for (int d = N - 1; d >= 1; d--) {
+        pa -= c[d] * (double)(a->p[d] - 1);
+        pb -= c[d] * (double)(b->p[d] - 1);
+        if (pa != pb)
+            return pa < pb;
+    }
     return memcmp(a->p, b->p, (size_t)N) < 0;
 }
 
-static void heap_push(pv_entry *h, int *n, const pv_entry *e, int N)
+static void heap_push(pv_entry *h, int *n, const pv_entry *e, int N, const double *c)
 {
     int i = (*n)++;
     h[i] = *e;
     while (i > 0) {
         int parent = (i - 1) / 2;
-        if (!pv_before(&h[i], &h[parent], N))
+        if (!pv_before(&h[i], &h[parent], N, c))
             break;
         pv_entry t = h[i];
         h[i] = h[parent];
@@ -431,16 +442,16 @@ static void heap_push(pv_entry *h, int *n, const pv_entry *e, int N)
     }
 }
 
-static pv_entry heap_pop(pv_entry *h, int *n, int N)
+static pv_entry heap_pop(pv_entry *h, int *n, int N, const double *c)
 {
     pv_entry top = h[0];
     h[0] = h[--(*n)];
     int i = 0;
     for (;;) {
         int l = 2 * i + 1, r = l + 1, m = i;
-        if (l < *n && pv_before(&h[l], &h[m], N))
+        if (l < *n && pv_before(&h[l], &h[m], N, c))
             m = l;
-        if (r < *n && pv_before(&h[r], &h[m], N))
+        if (r < *n && pv_before(&h[r], &h[m], N, c))
             m = r;
         if (m == i)
             break;
@@ -483,10 +494,10 @@ int orc_position_set(const double *w_depth, int N, int nq, int n_paths,
     for (int d = 0; d < N; d++)
         root.p[d] = 1;
     root.score = pv_score(c, root.p, N);
-    heap_push(h, &n, &root, N);
+    heap_push(h, &n, &root, N, c);
     double last_score = 0.0;
     for (int k = 0; k <= K && n > 0; k++) {
-        pv_entry e = heap_pop(h, &n, N);
+        pv_entry e = heap_pop(h, &n, N, c);
         if (k == K) {
             if (boundary_margin)
                 *boundary_margin = rel_gap(last_score, e.score);
@@ -505,7 +516,7 @@ int orc_position_set(const double *w_depth, int N, int nq, int n_paths,
                 pv_entry ch = e;
                 ch.p[j]++;
                 ch.score = pv_score(c, ch.p, N);
-                heap_push(h, &n, &ch, N);
+                heap_push(h, &n, &ch, N, c);
             }
     }
     if (K == total && boundary_margin)
@@ -515,14 +526,15 @@ int orc_position_set(const double *w_depth, int N, int nq, int n_paths,
 }
 
 /* Brute force over all |Q|^N vectors (tiny sizes only): score every one,  */
-/* sort by (score, lexicographic), keep the first K.                        */
+/* sort by the key above, keep the first K.                                 */
 static int g_sort_n;
+static const double *g_sort_c;
 static int pv_cmp(const void *a, const void *b)
 {
     const pv_entry *x = a, *y = b;
-    if (pv_before(x, y, g_sort_n))
+    if (pv_before(x, y, g_sort_n, g_sort_c))
         return -1;
-    if (pv_before(y, x, g_sort_n))
+    if (pv_before(y, x, g_sort_n, g_sort_c))
         return 1;
     return 0;
 }
@@ -552,6 +564,7 @@ int orc_position_set_brute(const double *w_depth, int N, int nq, int n_paths,
             cur[d]++;
     }
     g_sort_n = N;
+    g_sort_c = c;
     qsort(all, (size_t)total, sizeof(pv_entry), pv_cmp);
     int K = (long)n_paths < total ? n_paths : (int)total;
     for (int k = 0; k < K; k++) {

@@ -2,9 +2,12 @@
 // E wavefronts, one list entry per lane.
 //
 // Same definition as posvec_kernel (prep.hip): the K cheapest position
-// vectors in (cost, lexicographic) order, cost = sum_d c_d (p_d - 1) in
-// exact integers (cost_unit).  Depth by depth the list of the K cheapest
-// prefixes A is extended by rank doubling:
+// vectors, cost = sum_d c_d (p_d - 1) in exact integers (cost_unit), equal
+// costs ordered by the cost of the longest prefix, then the next shorter,
+// and equal prefix costs throughout lexicographically: the key
+// (C_N, C_{N-1}, ..., C_1, p), which is exactly (cost, position of the
+// parent prefix in its own sorted list, k) applied depth by depth.  Depth by
+// depth the list of the K cheapest prefixes A is extended by rank doubling:
 //     U_0 = A (rank 0 at this depth),   U_{j+1} = topK(U_j  U  raise(U_j, 2^j)),
 // where raise(., c) adds c to the last rank (cost parent + c_d k), so U_j
 // holds the K cheapest extensions with rank below 2^j; log2 |Q| merges cover
@@ -17,9 +20,9 @@
 // the K smallest.  The half cleaner and each stage across wavefronts go
 // through LDS (alternating buffers, one barrier each), the stages inside a
 // wavefront use DPP / row-swap lane exchanges.  An entry is one 64-bit key,
-// cost << 32 | packed with packed = parent position (12 bits) | k (6 bits)
-// << 12 | lexical rank of the parent (14 bits) << 18, so that (cost, parent
-// rank, k) compares as one unsigned integer.
+// cost << 32 | parent position << 6 | k, so that (cost, parent, k) compares
+// as one unsigned integer; an entry of A is its own parent with k = 0 at the
+// next depth, so no rank of the new list has to be computed.
 #include "device_common.h"
 
 #include <algorithm>
@@ -88,19 +91,15 @@ struct PosLds {
     static constexpr int KP = 64 * E;
     uint64_t xk[2][2][KP]; // exchange: [buffer][Z | B] keys
     uint64_t bck[2];       // broadcast of entry K-1 of Z
-    uint64_t akK1;         // key of entry K - 1 of A
-    uint32_t scA[KP];      // costs of list A by position
-    uint32_t cnt[KP];      // children per parent lexical rank
-    uint32_t run[KP];      // exclusive prefix of cnt inside each wavefront
-    uint32_t wsum[E];      // cnt total of each wavefront
-    uint32_t ap0;          // packed word of entry 0 of A
+    uint64_t akK1[2];      // key of entry K - 1 of A (two buffers, as scA)
+    uint32_t scA[2][KP];   // costs of list A by position: the current list and the next
 };
 
 // LDS of one workgroup: PosLds, then N * KP back pointers per depth, 16 bits
-// each (parent position | k << 8).  For 256 paths and N = 16 that is 20 KB,
+// each (parent position | k << 8).  For 256 paths and N = 16 that is 18 KB,
 // so eight workgroups fit a compute unit and a 1200-subcarrier slot runs in a
 // single round of workgroups.  REC_LDS = false: the back pointers live in
-// global memory (PosArgs::rec16) and the LDS holds PosLds only (12 KB for 256
+// global memory (PosArgs::rec16) and the LDS holds PosLds only (10 KB for 256
 // paths), for slots where the larger count saves a round.
 template <int E, bool REC_LDS = true>
 constexpr size_t pos_lds_bytes(int N)
@@ -119,12 +118,10 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
     const int K = a.K, N = a.N, nq = a.nq;
 
     uint64_t Ak = g == 0 ? 0ull : kNone;  // the root: cost 0, packed 0
-    sh.scA[g] = key_cost(Ak);
-    sh.cnt[g] = 0;
-    if (g == 0)
-        sh.ap0 = 0u;
+    int cur = 0;                          // buffer of the current list A
+    sh.scA[0][g] = key_cost(Ak);
     if (g == K - 1)
-        sh.akK1 = Ak;
+        sh.akK1[0] = Ak;
     // the depth costs, lane d holding c_d (N <= 32), read per depth from a
     // register instead of a dependent load
     const double wl = lane < N ? a.w[(size_t)s * N + lane] : 0.0;
@@ -138,20 +135,19 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
     int buf = 0;
     for (int d = 0; d < N; ++d) {
         const uint32_t c = lane_read(cl, d);
-        uint64_t Z = Ak;
-        const uint32_t a0s = sh.scA[0];
-        const uint32_t a0p = sh.ap0;
+        uint64_t Z = Ak;  // every entry of A as parent with k = 0
+        const uint32_t *scA = sh.scA[cur];
+        const uint32_t a0s = scA[0];
         // A full list that not even the cheapest entry with rank 2 at this
         // depth (entry 0 raised by one) can enter: every prefix extends by
-        // rank 1 only, so positions, costs and lexical ranks stay as they
-        // are and only the back pointers (parent = itself, k = 0) are
-        // written; no LDS state changes, no barrier.  (The merge loop below
-        // would stop at its first check and the rank pass reproduce the
-        // ranks.)  The decision reads LDS written before the last barrier,
-        // so every lane takes it alike.
+        // rank 1 only, so positions and costs stay as they are and only the
+        // back pointers (parent = itself, k = 0) are written; no LDS state
+        // changes, no barrier.  (The merge loop below would stop at its
+        // first check.)  The decision reads LDS written before the last
+        // barrier, so every lane takes it alike.
         if (d > 0) {
-            const uint64_t last = sh.akK1;
-            if (last != kNone && !(pkey(a0s + c, (a0p & 0xfffc0fffu) | (1u << 12)) < last)) {
+            const uint64_t last = sh.akK1[cur];
+            if (last != kNone && !(pkey(a0s + c, 1u) < last)) {
                 if (Ak != kNone)
                     rec[(size_t)d * KP + g] = (uint16_t)(g & 0xff);
                 continue;
@@ -161,15 +157,15 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
         // are already in key order (costs non-decreasing in k, equal costs
         // ordered by k), so entry g is child g and no merge is needed.
         if (d == 0)
-            Z = g < min(nq, K) ? pkey(c * (uint32_t)g, (uint32_t)g << 12) : kNone;
+            Z = g < min(nq, K) ? pkey(c * (uint32_t)g, (uint32_t)g) : kNone;
         // Z covers the ranks k < span of this depth; merging Z with its copy
         // raised by span covers k < 2 span (|Q| is a power of two, so the
         // raised ranks never pass |Q| - 1)
         for (int span = d == 0 ? nq : 1; span < nq; span <<= 1) {
             const bool ok = Z != kNone;
             const uint32_t zp = key_packed(Z);
-            const uint32_t k1 = ((zp >> 12) & 63) + (uint32_t)span;
-            const uint64_t B = ok ? pkey(sh.scA[ok ? (zp & 0xfff) : 0] + c * k1, zp + ((uint32_t)span << 12)) : kNone;
+            const uint32_t k1 = (zp & 63) + (uint32_t)span;
+            const uint64_t B = ok ? pkey(scA[ok ? (zp >> 6) : 0] + c * k1, zp + (uint32_t)span) : kNone;
             uint64_t l, m;
             if constexpr (E == 1) {
                 l = lane_read(Z, K - 1);
@@ -185,7 +181,7 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
             }
             // stop when the cheapest entry with rank span can no longer
             // enter a full list (the same decision in every lane)
-            if (l != kNone && !(pkey(a0s + c * (uint32_t)span, (a0p & 0xfffc0fffu) | ((uint32_t)span << 12)) < l))
+            if (l != kNone && !(pkey(a0s + c * (uint32_t)span, (uint32_t)span) < l))
                 break;
             if constexpr (E > 1) {
                 // half cleaner (entry g against entry KP - 1 - g of B), then
@@ -215,40 +211,21 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
             if (g >= K)
                 Z = kNone;
         }
-        // lexical ranks of the new prefixes: the children of a parent are
-        // k = 0..c-1, consecutive in lexical order.  cnt[] is zero here (set
-        // at the start and cleared by its reader below).
-        const uint32_t zp = key_packed(Z);
-        if (Z != kNone)
-            atomicMax(&sh.cnt[zp >> 18], ((zp >> 12) & 63) + 1);
-        __syncthreads();
-        {
-            const uint32_t v = sh.cnt[g];
-            sh.cnt[g] = 0;
-            const uint32_t incl = wave_scan_incl(v);
-            if (E > 1 && lane == 63)
-                sh.wsum[wv] = incl;
-            sh.run[g] = incl - v;  // exclusive prefix inside the wavefront
-        }
-        __syncthreads();
+        // the new list: back pointers, and every entry the parent of rank 0
+        // at the next depth
         if (Z != kNone) {
-            const uint32_t k = (zp >> 12) & 63;
-            const uint32_t pr = zp >> 18;  // parent's lexical rank
-            uint32_t base = 0;
-#pragma unroll
-            for (int j = 0; j < E - 1; ++j)
-                base += (uint32_t)j < (pr >> 6) ? sh.wsum[j] : 0u;
-            const uint32_t lx = sh.run[pr] + base + k;
-            rec[(size_t)d * KP + g] = (uint16_t)((zp & 0xffu) | (k << 8));  // parent position < 256
-            Ak = pkey(key_cost(Z), (uint32_t)g | (lx << 18));
+            const uint32_t zp = key_packed(Z);
+            rec[(size_t)d * KP + g] = (uint16_t)(((zp >> 6) & 0xffu) | ((zp & 63u) << 8));  // parent < 256
+            Ak = pkey(key_cost(Z), (uint32_t)g << 6);
         } else {
             Ak = kNone;
         }
-        sh.scA[g] = key_cost(Ak);
-        if (g == 0)
-            sh.ap0 = key_packed(Ak);
+        // into the other buffer (its last readers passed the barrier that
+        // ended the previous depth), then one barrier
+        sh.scA[cur ^ 1][g] = key_cost(Ak);
         if (g == K - 1)
-            sh.akK1 = Ak;
+            sh.akK1[cur ^ 1] = Ak;
+        cur ^= 1;
         __syncthreads();
     }
 

@@ -250,9 +250,10 @@ __global__ __launch_bounds__(64) void sqrd_batch_kernel(const StageJob *jobs, in
 //     Z_0 = list,  Z_m = topK(list  U  shift(Z_{m-1})),
 // stopping when the cheapest entry with p_d = m+1 can no longer enter.
 // Each merge is a merge-path over two sorted lists in LDS.  Ties in cost are
-// ordered by the lexical rank of the parent prefix, then k, which is the
-// lexicographic order of the extended prefixes.  Back pointers
-// (parent, k) per depth rebuild the vectors at the end.
+// ordered by the position of the parent prefix in its sorted list, then k:
+// the key (C_N, C_{N-1}, ..., C_1, p) of the definition, C_j the cost of the
+// first j depths.  Back pointers (parent, k) per depth rebuild the vectors
+// at the end.
 // ============================================================================
 
 __device__ __forceinline__ bool key_less(uint32_t sa, int la, int ka, uint32_t sb, int lb, int kb)
@@ -270,16 +271,12 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
 
     uint32_t *A_sc = (uint32_t *)smem;
     uint32_t *Zs[2] = {A_sc + K, A_sc + 2 * K};
-    uint16_t *A_lx = (uint16_t *)(A_sc + 3 * K);
-    uint16_t *Zp[2] = {A_lx + K, A_lx + 2 * K};
-    uint16_t *Zk[2] = {A_lx + 3 * K, A_lx + 4 * K};
-    uint32_t *cnt = (uint32_t *)(A_lx + ((5 * K + 1) & ~1));
-    uint32_t *rec = REC_LDS ? (cnt + K) : (a.rec_g + (size_t)s * N * K);
+    uint16_t *Zp[2] = {(uint16_t *)(A_sc + 3 * K), (uint16_t *)(A_sc + 3 * K) + K};
+    uint16_t *Zk[2] = {Zp[1] + K, Zp[1] + 2 * K};
+    uint32_t *rec = REC_LDS ? (uint32_t *)(Zp[0] + ((4 * K + 1) & ~1)) : (a.rec_g + (size_t)s * N * K);
 
-    if (lane == 0) {
+    if (lane == 0)
         A_sc[0] = 0u;
-        A_lx[0] = 0;
-    }
     int n = 1;
     double wmax = 0.0;
     for (int d = 0; d < N; ++d)
@@ -300,7 +297,7 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
             if (zn == K) {
                 const uint32_t nm = A_sc[0] + cd * (uint32_t)m;
                 const int zp = Zp[cur][K - 1];
-                if (!key_less(nm, A_lx[0], m, Zs[cur][K - 1], A_lx[zp], Zk[cur][K - 1]))
+                if (!key_less(nm, 0, m, Zs[cur][K - 1], zp, Zk[cur][K - 1]))
                     break;
             }
             // merge list A (k = 0) with B = shift(Z_cur) into Z_nxt
@@ -319,7 +316,7 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
                     const int par = zp[j];
                     const int kb = zk[j] + 1;
                     const uint32_t sb = A_sc[par] + cd * (uint32_t)kb;
-                    if (key_less(A_sc[mid], A_lx[mid], 0, sb, A_lx[par], kb))
+                    if (key_less(A_sc[mid], mid, 0, sb, par, kb))
                         lo = mid + 1;
                     else
                         hi = mid;
@@ -339,7 +336,7 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
                     else if (j >= zn)
                         takeA = true;
                     else
-                        takeA = key_less(A_sc[i], A_lx[i], 0, sb, A_lx[par], kb);
+                        takeA = key_less(A_sc[i], i, 0, sb, par, kb);
                     if (takeA) {
                         Zs[nxt][p] = A_sc[i];
                         Zp[nxt][p] = (uint16_t)i;
@@ -357,42 +354,8 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
             cur = nxt;
             zn = total;
         }
-        // lexical ranks of the new prefixes: children of a parent are k = 0..c-1
-        for (int i = lane; i < n; i += 64)
-            cnt[i] = 0;
-        __syncthreads();
-        for (int j = lane; j < zn; j += 64)
-            atomicMax(&cnt[A_lx[Zp[cur][j]]], (uint32_t)Zk[cur][j] + 1u);
-        __syncthreads();
-        {  // exclusive scan of cnt[0..n)
-            const int ch = (n + 63) / 64;
-            const int q0 = min(n, lane * ch), q1 = min(n, q0 + ch);
-            uint32_t local = 0;
-            for (int q = q0; q < q1; ++q)
-                local += cnt[q];
-            uint32_t incl = local;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t v = __shfl_up(incl, off);
-                if (lane >= off)
-                    incl += v;
-            }
-            uint32_t run = incl - local;
-            for (int q = q0; q < q1; ++q) {
-                const uint32_t v = cnt[q];
-                cnt[q] = run;
-                run += v;
-            }
-        }
-        __syncthreads();
-        // new list; ranks go to the idle ping-pong buffer before A_lx is overwritten
-        uint16_t *newlx = Zk[cur ^ 1];
-        for (int j = lane; j < zn; j += 64)
-            newlx[j] = (uint16_t)(cnt[A_lx[Zp[cur][j]]] + Zk[cur][j]);
-        __syncthreads();
         for (int j = lane; j < zn; j += 64) {
             A_sc[j] = Zs[cur][j];
-            A_lx[j] = newlx[j];
             rec[(size_t)d * K + j] = (uint32_t)Zp[cur][j] | ((uint32_t)Zk[cur][j] << 16);
         }
         n = zn;
@@ -627,8 +590,7 @@ bool posvec_rec_fits_lds(int N, int K)
 size_t posvec_lds_bytes(int N, int K, bool rec_in_lds)
 {
     size_t b = (size_t)K * 3 * sizeof(uint32_t);         // A_sc, Zs[2]
-    b += (size_t)((5 * K + 1) & ~1) * sizeof(uint16_t);  // A_lx, Zp[2], Zk[2]
-    b += (size_t)K * sizeof(uint32_t);                    // cnt
+    b += (size_t)((4 * K + 1) & ~1) * sizeof(uint16_t);  // Zp[2], Zk[2]
     if (rec_in_lds)
         b += (size_t)N * K * sizeof(uint32_t);
     return b;

@@ -106,12 +106,16 @@ def np_depth_costs(w_depth):
 
 
 def np_position_set(w_depth, nq, K):
-    """All |Q|^N vectors (depth order, entries 1..nq), sorted by integer cost
-    then lexicographically; -> (first K vectors, boundary margin)."""
+    """All |Q|^N vectors (depth order, entries 1..nq), sorted by integer cost,
+    equal costs by the costs of the prefixes (longest first), then
+    lexicographically; -> (first K vectors, boundary margin)."""
     N = len(w_depth)
     P = np.array(list(itertools.product(range(1, nq + 1), repeat=N)), dtype=np.int64)
-    score = ((P - 1) @ np_depth_costs(w_depth).astype(np.int64)).astype(np.float64)
-    keys = [P[:, d] for d in range(N - 1, -1, -1)] + [score]
+    terms = (P - 1) * np_depth_costs(w_depth).astype(np.int64)[None, :]
+    prefix = np.cumsum(terms, axis=1)          # prefix[:, j - 1] = cost of the first j depths
+    score = prefix[:, -1].astype(np.float64)
+    # np.lexsort: the last key is the primary one
+    keys = [P[:, d] for d in range(N - 1, -1, -1)] + [prefix[:, j] for j in range(N)]
     order = np.lexsort(keys)
     P, score = P[order], score[order]
     K = min(K, len(P))

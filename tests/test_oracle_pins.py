@@ -114,14 +114,20 @@ def test_position_set_equals_brute_force(N, nq, K, seed):
 
 
 @pytest.mark.parametrize("w", [[1.0, 1.0, 1.0], [0.0, 2.0, 0.0], [0.0, 0.0, 0.0], [3.0, 1.5, 0.5]])
-def test_position_set_ties_are_lexicographic(w):
+def test_position_set_ties_by_prefix_costs_then_lexicographic(w):
     w = np.array(w)
     P, sc, bm = oracle.position_set(w, 4, 64)
     P2, sc2 = oracle.position_set_brute(w, 4, 64)
     assert np.array_equal(P, P2)
-    # explicit check of the (score, lexicographic) order
-    keys = [(s, tuple(p)) for s, p in zip(sc, P.tolist())]
+    # explicit check of the order: (C_N, C_{N-1}, ..., C_1, p lexicographic),
+    # C_j the cost of the first j depths, from the integer depth costs
+    c = [round(x / max(w) * 2 ** 20) if max(w) > 0 else 0 for x in w]
+    def key(p):
+        pre = [sum(c[e] * (p[e] - 1) for e in range(j)) for j in range(len(p), 0, -1)]
+        return tuple(pre) + tuple(p)
+    keys = [key(p) for p in P.tolist()]
     assert keys == sorted(keys)
+    assert [k[0] for k in keys] == sc.tolist()
 
 
 @pytest.mark.parametrize("w,c1", [([1.0, 2.5 * 2.0 ** -20], 2),    # 2.5 units: half to even, down
