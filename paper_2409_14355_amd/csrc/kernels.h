@@ -112,7 +112,7 @@ struct StageJob;
 hipError_t launch_sqrd_batch(const dev::StageJob *jobs, int n_jobs, int items, int mmax, hipStream_t st);
 hipError_t launch_posvec_batch(const dev::StageJob *jobs, int n_jobs, int items, int E, int Nmax,
                                hipStream_t st);
-hipError_t launch_rotate_batch(const dev::StageJob *jobs, int n_jobs, int items, hipStream_t st);
+hipError_t launch_rotate_batch(const dev::StageJob *jobs, int n_jobs, int items, int nmax, hipStream_t st);
 size_t posvec_reg_lds_bytes(int N, int K);
 // Whether a slot's 256-path position set keeps its back pointers in global
 // memory (SlotDev::rec16): when, with cus compute units of lds_per_cu bytes of

@@ -1152,6 +1152,7 @@ size_t plan_layout(mpnl_batch *p, bool prune, int phases = 1)
                 } else if (stage == L_ROTATE) {
                     L = &group(phase, L_ROTATE, 0, 0, 64);
                     L->items += j.S;
+                    L->nmax = std::max(L->nmax, j.N);
                 } else {
                     L = &group(phase, L_PATHS, j.N, j.mod, (K + 63) / 64 * 64);
                     L->items += j.S * j.T;
@@ -1347,7 +1348,7 @@ hipError_t plan_enqueue(mpnl_batch *p, int b, hipStream_t st, mpnl_ctx *timed = 
         }
         case L_ROTATE: {
             StageTimer tm(tc, MPNL_STAGE_ROTATE, st);
-            e = mpnl::launch_rotate_batch((const mpnl::dev::StageJob *)tab, nj, L.items, st);
+            e = mpnl::launch_rotate_batch((const mpnl::dev::StageJob *)tab, nj, L.items, L.nmax, st);
             break;
         }
         default:
