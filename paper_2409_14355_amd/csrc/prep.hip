@@ -243,8 +243,8 @@ __global__ __launch_bounds__(64) void sqrd_batch_kernel(const StageJob *jobs, in
 // a2: position-vector set.
 // The cost of a position vector is sum_d c_d (p_d - 1) in exact integers
 // (cost_unit: the depth weights scaled to 2^kCostBits of the largest and
-// rounded).  Depth by depth, the list of the K cheapest prefixes (in (cost,
-// lexical) order) is extended: candidates are (prefix i, k) with cost
+// rounded).  Depth by depth, the list of the K cheapest prefixes (in key
+// order, below) is extended: candidates are (prefix i, k) with cost
 // sc_i + c_d k, k = 0..|Q|-1.  Because every copy "list + k c_d" is a
 // shifted copy of the sorted list, the top-K of their union is built as
 //     Z_0 = list,  Z_m = topK(list  U  shift(Z_{m-1})),
