@@ -89,6 +89,28 @@ def test_plan_replays_equal_alone(ctx, autotune, serial):
         plan.close()
 
 
+@pytest.mark.parametrize("serial", [False, True])
+def test_plan_single_path_group_equals_alone(ctx, serial):
+    """Jobs that all share one path-search group (same users, constellation
+    and lanes): with two pipeline phases the second phase has no jobs."""
+    shapes = [(70, 14, 10, 8, 4, 128), (33, 5, 8, 8, 4, 100), (51, 14, 16, 8, 4, 128)]
+    _say("batch plan, one path group, serial", serial)
+    plan = ctx.batch_plan([dict(S=S, T=T, M=M, N=N, mod=b, n_paths=K) for S, T, M, N, b, K in shapes],
+                          serial=serial)
+    try:
+        assert len(plan.launch_shapes()) == 1
+        for rep in range(2):
+            jobs, _ = _jobs(shapes, 700 + rep)
+            plan.run(jobs)
+            torch.cuda.synchronize()
+            for j in jobs:
+                alone = ctx.detect(j["H"], j["y"], j["mod"], j["n_paths"])
+                torch.cuda.synchronize()
+                assert torch.equal(alone, j["out"]), (rep, j["H"].shape)
+    finally:
+        plan.close()
+
+
 def test_plan_two_in_flight_and_rebind(ctx):
     """Back-to-back runs without a host wait use both table copies; each run
     writes only its own outputs."""
