@@ -184,6 +184,45 @@ def test_plan_forty_cells_full_size(ctx):
         plan.close()
 
 
+def test_plan_forty_cells_fp16_headline(ctx):
+    """The benchmark's configuration: the forty cells of seed (2, 0) at full
+    size, FP16 path metrics, two pipeline phases.  Every job equals its alone
+    run in FP16; against the FP64 oracle on sampled subcarriers of five cells
+    at most 0.6% of the vectors differ (the FP16 bound of the precision
+    tests at 8 dB; these slots are at 16 dB)."""
+    cells = synth.draw_cells(40, seed=(2, 0))
+    shapes = [(c.S, 14, c.M, c.N, c.bits, c.n_paths) for c in cells]
+    _say("forty cells fp16 headline", shapes[:3], "...")
+    ctx.set_precision(1)
+    try:
+        plan = ctx.batch_plan([dict(S=S, T=T, M=M, N=N, mod=b, n_paths=K) for S, T, M, N, b, K in shapes],
+                              autotune=True)
+        try:
+            jobs, slots = _jobs(shapes, 360)
+            plan.run(jobs)
+            torch.cuda.synchronize()
+            for j in jobs:
+                alone = ctx.detect(j["H"], j["y"], j["mod"], j["n_paths"])
+                torch.cuda.synchronize()
+                assert torch.equal(alone, j["out"])
+            rng = np.random.default_rng(361)
+            diff = total = 0
+            for i in (0, 9, 18, 27, 36):
+                sl, K = slots[i], shapes[i][5]
+                sub = np.sort(rng.choice(sl.H.shape[0], size=16, replace=False))
+                got = jobs[i]["out"].cpu().numpy()[:, sub]
+                ref = oracle.detect_slot("mpnl", sl.H[sub], np.ascontiguousarray(sl.y[:, sub]), sl.bits,
+                                         n_paths=K, nthreads=8)
+                diff += int(np.any(got != ref, axis=-1).sum())
+                total += ref.shape[0] * ref.shape[1]
+            print(f"forty cells fp16: {diff} of {total} sampled vectors differ from FP64", flush=True)
+            assert diff <= 0.006 * total
+        finally:
+            plan.close()
+    finally:
+        ctx.set_precision(0)
+
+
 @pytest.mark.parametrize("prec", [1, 2])
 def test_plan_reduced_precision_equals_alone(ctx, prec):
     """A plan made under FP16 / BF16 path metrics gives what detect gives
