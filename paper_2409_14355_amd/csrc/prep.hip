@@ -125,8 +125,11 @@ __device__ __forceinline__ void sqrd_body(const SqrdArgs &a, int pair)
 #pragma unroll
             for (int m = i; m < MMAX; ++m) {
                 const float2 v = V[half][i][m];
-                col[m].x -= gr * v.x - gi * v.y;
-                col[m].y -= gr * v.y + gi * v.x;
+                // col -= g v as two FMAs a component (a product-then-
+                // difference form took a multiply, an FMA and a subtraction;
+                // a1 of 40 cells 0.96 -> 0.89 ms)
+                col[m].x = fmaf(gi, v.y, fmaf(-gr, v.x, col[m].x));
+                col[m].y = fmaf(-gi, v.x, fmaf(-gr, v.y, col[m].y));
             }
             const float2 ph = PHI[half][i];  // row i *= conj(phi_i)
             const float xr = col[i].x * ph.x + col[i].y * ph.y;
@@ -199,8 +202,8 @@ __device__ __forceinline__ void sqrd_body(const SqrdArgs &a, int pair)
 #pragma unroll
             for (int m = j; m < MMAX; ++m) {
                 const float2 v = V[half][j][m];
-                q[m].x -= gr * v.x - gi * v.y;
-                q[m].y -= gr * v.y + gi * v.x;
+                q[m].x = fmaf(gi, v.y, fmaf(-gr, v.x, q[m].x));
+                q[m].y = fmaf(-gi, v.x, fmaf(-gr, v.y, q[m].y));
             }
         }
     }
