@@ -91,8 +91,10 @@ __device__ __forceinline__ void sqrd_body(const SqrdArgs &a, int pair)
             const float2 x0 = col[i];
             const float ax0 = sqrtf(x0.x * x0.x + x0.y * x0.y);
             float2 e = make_float2(1.f, 0.f);
-            if (ax0 > 0.f)
-                e = make_float2(x0.x / ax0, x0.y / ax0);
+            if (ax0 > 0.f) {
+                const float r = 1.f / ax0;  // one division for both components
+                e = make_float2(x0.x * r, x0.y * r);
+            }
 #pragma unroll
             for (int m = 0; m < MMAX; ++m) {
                 float2 v = (m < i) ? make_float2(0.f, 0.f) : col[m];
