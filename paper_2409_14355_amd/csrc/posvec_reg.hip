@@ -231,14 +231,13 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
 
     // rebuild the position vectors (ranks 1..|Q|), rows padded with 1, and
     // note for each which depths ask for a rank >= 3 and >= 2
-    const int nw = a.NP >> 2;
     const int r = g;
     uint64_t ks = kNone;  // sort key of path r; paths past K sort last
     if (r < K) {
-        uint32_t wvd[kMaxN / 4];
-#pragma unroll
-        for (int q = 0; q < kMaxN / 4; ++q)
-            wvd[q] = 0x01010101u;
+        // one word of four depths at a time, written when its lowest depth
+        // is in (the top word keeps its padding bytes)
+        uint32_t *dst = (uint32_t *)(a.P + ((size_t)s * a.K + r) * a.NP);
+        uint32_t w = 0x01010101u;
         uint32_t m5 = 0, m3 = 0, m2 = 0;
         int pidx = r;
         for (int d = N - 1; d >= 0; --d) {
@@ -248,16 +247,13 @@ __device__ __forceinline__ void posvec_body(const PosArgs &a, int s, unsigned ch
             m5 |= (pk >= 5u ? 1u : 0u) << d;
             m3 |= (pk >= 3u ? 1u : 0u) << d;
             m2 |= (pk >= 2u ? 1u : 0u) << d;
-#pragma unroll
-            for (int q = 0; q < kMaxN / 4; ++q)
-                if (q == (d >> 2))
-                    wvd[q] = (wvd[q] & ~(0xffu << ((d & 3) * 8))) | (pk << ((d & 3) * 8));
+            const uint32_t sh8 = (uint32_t)(d & 3) * 8u;
+            w = (w & ~(0xffu << sh8)) | (pk << sh8);
+            if ((d & 3) == 0) {
+                dst[d >> 2] = w;
+                w = 0x01010101u;
+            }
         }
-        uint32_t *dst = (uint32_t *)(a.P + ((size_t)s * a.K + r) * a.NP);
-#pragma unroll
-        for (int q = 0; q < kMaxN / 4; ++q)
-            if (q < nw)
-                dst[q] = wvd[q];
         // sort key: the first depth with a rank >= 2 (paths that leave the
         // first-choice path early are pruned early, and the pruning stops
         // whole wavefronts), the first depths with a rank >= 3 and >= 5 (the
