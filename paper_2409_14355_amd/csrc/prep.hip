@@ -367,28 +367,23 @@ __global__ __launch_bounds__(64) void posvec_kernel(PosArgs a)
         __syncthreads();
     }
 
-    // rebuild the position vectors (ranks 1..|Q|), rows padded with 1
-    const int nw = a.NP >> 2;
+    // rebuild the position vectors (ranks 1..|Q|), rows padded with 1: one
+    // word of four depths at a time, stored when its lowest depth is in
     for (int r = lane; r < n; r += 64) {
-        uint32_t wv[kMaxN / 4];
-#pragma unroll
-        for (int w = 0; w < kMaxN / 4; ++w)
-            wv[w] = 0x01010101u;
+        uint32_t *dst = (uint32_t *)(a.P + ((size_t)s * a.K + r) * a.NP);
+        uint32_t w = 0x01010101u;
         int pidx = r;
         for (int d = N - 1; d >= 0; --d) {
             const uint32_t e = rec[(size_t)d * K + pidx];
             const uint32_t pk = (e >> 16) + 1u;
             pidx = (int)(e & 0xffffu);
-#pragma unroll
-            for (int w = 0; w < kMaxN / 4; ++w)
-                if (w == (d >> 2))
-                    wv[w] = (wv[w] & ~(0xffu << ((d & 3) * 8))) | (pk << ((d & 3) * 8));
+            const uint32_t sh8 = (uint32_t)(d & 3) * 8u;
+            w = (w & ~(0xffu << sh8)) | (pk << sh8);
+            if ((d & 3) == 0) {
+                dst[d >> 2] = w;
+                w = 0x01010101u;
+            }
         }
-        uint32_t *dst = (uint32_t *)(a.P + ((size_t)s * a.K + r) * a.NP);
-#pragma unroll
-        for (int w = 0; w < kMaxN / 4; ++w)
-            if (w < nw)
-                dst[w] = wv[w];
     }
 }
 
