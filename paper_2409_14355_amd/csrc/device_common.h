@@ -292,87 +292,106 @@ __device__ __forceinline__ void axis_second(float z, float dz, float m0, float &
     e1 = square_rn(z - level_of<L>(m1));
 }
 
-// levels of rank 1..3 of one axis (rank 0 = m0, at level lv0): the zig-zag
-// from m0 that starts on the side of z, levels beyond the constellation
-// skipped.  With |z - lv0| <= 1 the zig-zag is sorted by distance; when z
-// lies beyond the outermost level only one side exists and the order is
-// monotone.  Missing ranks (L = 2) get infinite distances.
-template <int L>
-__device__ __forceinline__ void axis_ranks3(float z, float m0, float lv0, float (&m)[3], float (&e)[3])
+// Levels of rank 1..3 of one axis, rank 0 being the closest level m0: the
+// zig-zag from m0 that starts on the side of z, levels beyond the
+// constellation skipped.  With |z - lv0| <= 1 the zig-zag is sorted by
+// distance; when z lies beyond the outermost level only one side exists and
+// the order is monotone.  In mirrored coordinates (z at or above its closest
+// level m') the level index of rank t depends on m' alone:
+constexpr int zigzag_rank(int L, int mp, int t)
 {
-    if constexpr (L == 4) {
-        // Four levels: mirrored so that z lies at or above its closest level
-        // (m' = m0, or 3 - m0), ranks 1..3 are one of four rows, 2 bits a
-        // rank and 6 bits a row: m' = 0: 1 2 3; 1: 2 0 3; 2: 3 1 0; 3: 2 1 0.
-        // The same levels as the zig-zag below (exact small integers).
-        constexpr uint32_t kRows = 57u | (50u << 6) | (7u << 12) | (6u << 18);
-        const float s = __builtin_copysignf(1.f, z - lv0);  // +0 on the level: upward, as z >= level
-        const uint32_t row = kRows >> __umul24((uint32_t)fmaf(s, m0 - 1.5f, 1.5f), 6u);
-        const float c = fmaf(-1.5f, s, 1.5f);               // unmirror: m = s r + c
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const float mt = fmaf(s, (float)((row >> (2 * t)) & 3u), c);
-            m[t] = mt;
-            e[t] = square_rn(z - level_of<L>(mt));
-        }
-        return;
+    const int up = L - 1 - mp, down = mp;  // levels above and below m'
+    const int q = up < down ? up : down;
+    if (t <= 2 * q)
+        return (t & 1) ? mp + (t + 1) / 2 : mp - t / 2;
+    return up > down ? mp + (t - q) : mp - (t - q);
+}
+// ... tabulated for L = 4 and 8 as the mirrored level value v = 2 r - (L - 1)
+// of rank t, a signed field of 32 / L bits per m'
+constexpr uint32_t zigzag_word(int L, int t)
+{
+    uint32_t w = 0;
+    for (int mp = 0; mp < L; ++mp) {
+        const int v = 2 * zigzag_rank(L, mp, t) - (L - 1);
+        w |= ((uint32_t)v & ((1u << (32 / L)) - 1u)) << ((32 / L) * mp);
     }
-    const float s = (z >= lv0) ? 1.f : -1.f;
-    const float cp = s > 0.f ? (float)(L - 1) - m0 : m0;  // levels on side +s
-    const float cm = (float)(L - 1) - cp;                  // levels on side -s
-    const float q = fminf(cp, cm);
-    const float far = cp > cm ? s : -s;
+    return w;
+}
+
+// Ranks 1..3 of one axis (L = 4 or 8): mirrored level values v[t] and
+// squared distances e[t], with the mirror sign s (s = +1: z at or above the
+// level of m0, the level of rank t is s v[t]).  The distance is taken in
+// mirrored coordinates, (s z - v)^2: negation is exact and rounding
+// symmetric, so it is the same bits as (z - s v)^2.
+template <int L>
+__device__ __forceinline__ void axis_ranks3(float z, float m0, float lv0, float (&v)[3], float (&e)[3], float &s)
+{
+    static_assert(L == 4 || L == 8, "tabulated zig-zag: 4 or 8 levels an axis");
+    constexpr int FW = 32 / L;
+    constexpr float H = 0.5f * (float)(FW * (L - 1));
+    s = __builtin_copysignf(1.f, z - lv0);  // +0 on the level: upward, as z >= level
+    const float zs = s * z;
+    const uint32_t off = (uint32_t)fmaf(s, fmaf(m0, (float)FW, -H), H);  // FW m'
 #pragma unroll
-    for (int t = 1; t <= 3; ++t) {
-        const float ti = (t & 1) ? m0 + s * (float)((t + 1) / 2) : m0 - s * (float)(t / 2);
-        const float to = m0 + far * ((float)t - q);
-        const float mt = ((float)t <= 2.f * q) ? ti : to;
-        const float dd = z - level_of<L>(mt);
-        m[t - 1] = mt;
-        e[t - 1] = (t <= L - 1) ? square_rn(dd) : INFINITY;
+    for (int t = 0; t < 3; ++t) {
+        v[t] = (float)(int)__builtin_amdgcn_sbfe((int)zigzag_word(L, t + 1), off, FW);
+        e[t] = square_rn(zs - v[t]);
     }
 }
 
 // Exact 3rd or 4th closest point from the per-axis orders: ranks 2..4 of
-// the sum of two sorted lists lie on the frontier {(1,0), (0,1)}, then
-// {(2,0), (0,1)} or {(1,0), (0,2)}, then one of (3,0), (2,0), (1,1), (0,2),
-// (0,3) depending on the earlier ranks.  Equal costs: the in-phase step first.
+// the sum of two sorted lists come from the in-phase chain (t, 0), the
+// quadrature chain (0, t) and the corner (1, 1), which can only follow both
+// (1, 0) and (0, 1): the frontier {(1,0), (0,1)}, then {(2,0), (0,1)} or
+// {(1,0), (0,2)}, then one of (3,0), (2,0), (1,1), (0,2), (0,3) depending on
+// the earlier ranks.  Equal costs: the larger in-phase step first.  Every
+// lane evaluates the same compares and the choice is a few selects (no
+// divergent branches); returns the point's squared distance, the sum of the
+// two axes' distances as for any other rank.
 template <int L>
-__device__ __forceinline__ void kth_small(float zI, float zQ, int k, float &mI, float lI, float &eI,
-                                          float &mQ, float lQ, float &eQ)
+__device__ __forceinline__ float kth_small(float zI, float zQ, int k, float &mI, float lI, float eI,
+                                           float &mQ, float lQ, float eQ)
 {
-    float mi[3], ei[3], mq[3], eq[3];
-    axis_ranks3<L>(zI, mI, lI, mi, ei);
-    axis_ranks3<L>(zQ, mQ, lQ, mq, eq);
-    const float e0I = eI, e0Q = eQ;
-    const float c10 = ei[0] + e0Q, c01 = e0I + eq[0];
-    const float c20 = ei[1] + e0Q, c02 = e0I + eq[1];
-    const bool firstI = c10 <= c01;
-    const bool third20 = firstI & (c20 <= c01);   // ranks 2, 3 = (1,0), (2,0)
-    const bool third02 = !firstI & (c02 < c10);   // ranks 2, 3 = (0,1), (0,2)
-    int ci, cj;
-    if (k == 3) {
-        ci = firstI ? (third20 ? 2 : 0) : (third02 ? 0 : 1);
-        cj = firstI ? (third20 ? 0 : 1) : (third02 ? 2 : 0);
-    } else if (third20) {
-        const bool a = ei[2] + e0Q <= c01;       // (3,0) or (0,1)
-        ci = a ? 3 : 0;
-        cj = a ? 0 : 1;
-    } else if (third02) {
-        const bool a = c10 <= e0I + eq[2];       // (1,0) or (0,3)
-        ci = a ? 1 : 0;
-        cj = a ? 0 : 3;
+    if constexpr (L == 2) {
+        // two levels an axis: rank 3 is the single step rank 2 did not
+        // take, rank 4 the corner
+        const float m1I = 1.f - mI, m1Q = 1.f - mQ;
+        const float e1I = square_rn(zI - level_of<L>(m1I)), e1Q = square_rn(zQ - level_of<L>(m1Q));
+        const float A1 = e1I + eQ, B1 = eI + e1Q;
+        const bool firstI = A1 <= B1;
+        const bool inI = (k == 3) & !firstI, inQ = (k == 3) & firstI;
+        mI = inQ ? mI : m1I;
+        mQ = inI ? mQ : m1Q;
+        return inI ? A1 : inQ ? B1 : e1I + e1Q;
     } else {
-        const float c11 = ei[0] + eq[0];         // (2,0), (1,1) or (0,2)
-        const bool a = (c20 <= c11) & (c20 <= c02);
-        const bool b = !a & (c11 <= c02);
-        ci = a ? 2 : b ? 1 : 0;
-        cj = a ? 0 : b ? 1 : 2;
+        float vi[3], ei[3], vq[3], eq[3], sI, sQ;
+        axis_ranks3<L>(zI, mI, lI, vi, ei, sI);
+        axis_ranks3<L>(zQ, mQ, lQ, vq, eq, sQ);
+        const float A1 = ei[0] + eQ, A2 = ei[1] + eQ, A3 = ei[2] + eQ;  // (t, 0)
+        const float B1 = eI + eq[0], B2 = eI + eq[1], B3 = eI + eq[2];  // (0, t)
+        const float C = ei[0] + eq[0];                                  // (1, 1)
+        const bool firstI = A1 <= B1;          // rank 2 = (1,0), else (0,1)
+        const bool t20 = firstI & (A2 <= B1);  // ranks 2, 3 = (1,0), (2,0)
+        const bool t02 = !firstI & (B2 < A1);  // ranks 2, 3 = (0,1), (0,2)
+        const bool k3 = k == 3;
+        // rank 4 after (1,0), (2,0): (3,0) or (0,1); after (0,1), (0,2):
+        // (1,0) or (0,3); after (1,0), (0,1): (2,0), (1,1) or (0,2)
+        const bool mid = !t20 & !t02;
+        const bool x20 = (A2 <= C) & (A2 <= B2), x11 = !x20 & (C <= B2);
+        const bool i1 = k3 ? (!firstI & !t02) : (t02 & (A1 <= B3));
+        const bool i2 = k3 ? t20 : (mid & x20);
+        const bool i3 = !k3 & t20 & (A3 <= B1);
+        const bool q1 = k3 ? (firstI & !t20) : (t20 & !(A3 <= B1));
+        const bool q2 = k3 ? t02 : (mid & !x20 & !x11);
+        const bool q3 = !k3 & t02 & !(A1 <= B3);
+        const bool c11 = !k3 & mid & x11;
+        // level index from the mirrored level value: m = (s v + L - 1) / 2
+        const float vI = i3 ? vi[2] : i2 ? vi[1] : vi[0];
+        const float vQ = q3 ? vq[2] : q2 ? vq[1] : vq[0];
+        mI = (i1 | i2 | i3 | c11) ? fmaf(vI, 0.5f * sI, 0.5f * (float)(L - 1)) : mI;
+        mQ = (q1 | q2 | q3 | c11) ? fmaf(vQ, 0.5f * sQ, 0.5f * (float)(L - 1)) : mQ;
+        return i1 ? A1 : i2 ? A2 : i3 ? A3 : q1 ? B1 : q2 ? B2 : q3 ? B3 : C;
     }
-    mI = ci == 0 ? mI : ci == 1 ? mi[0] : ci == 2 ? mi[1] : mi[2];
-    eI = ci == 0 ? e0I : ci == 1 ? ei[0] : ci == 2 ? ei[1] : ei[2];
-    mQ = cj == 0 ? mQ : cj == 1 ? mq[0] : cj == 2 ? mq[1] : mq[2];
-    eQ = cj == 0 ? e0Q : cj == 1 ? eq[0] : cj == 2 ? eq[1] : eq[2];
 }
 
 // Exact k-th closest point for k > 4, computed by the whole wavefront.  The
@@ -605,8 +624,7 @@ __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_
                 mQ = inI ? mQ : mQ1;
                 e = inI ? cI : cQ;
             } else if (k == 3 || k == 4) {
-                kth_small<L>(zI, zQ, k, mI, lI, eI, mQ, lQ, eQ);
-                e = eI + eQ;
+                e = kth_small<L>(zI, zQ, k, mI, lI, eI, mQ, lQ, eQ);
             }
             if constexpr (L > 2 && !FIRST)
                 kth_wave<L>(k > 4, zI, zQ, k, mI, mQ, e);
