@@ -418,25 +418,23 @@ __device__ __forceinline__ void kth_wave(bool need, float zI, float zQ, int k, f
         const float zi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zI), src));
         const float zq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zQ), src));
         const float dI = zi - vI, dQ = zq - vQ;
-        float key = square_rn(dI) + square_rn(dQ);
-        int kid = cidx;
+        // (cost, index) as one 64-bit key: costs are sums of squares (+0
+        // or more), whose bit patterns order as the values do
+        uint64_t key = lane_join((uint32_t)cidx, __float_as_uint(square_rn(dI) + square_rn(dQ)));
 #pragma unroll
         for (int size = 2; size <= NPT; size <<= 1) {
 #pragma unroll
             for (int j = size >> 1; j > 0; j >>= 1) {
-                const float ok = lane_xor_n(key, j);
-                const int oid = lane_xor_n(kid, j);
+                const uint64_t ok = lane_xor_n(key, j);
                 const bool up = size == NPT || (lane & size) == 0;
                 const bool lower = (lane & j) == 0;
-                const bool other_first = (ok < key) | ((ok == key) & (oid < kid));
-                const bool take = (lower == up) == other_first;
+                const bool take = (lower == up) == (ok < key);
                 key = take ? ok : key;
-                kid = take ? oid : kid;
             }
         }
         const bool mine = need && ((zI == zi && zQ == zq) || lane == src);
         const int from = (lane & ~(NPT - 1)) + min(max(k, 1), NPT) - 1;
-        const int got = __shfl(kid, from);
+        const int got = __shfl((int)(uint32_t)key, from);
         if (mine) {
             mI = (float)gray_decode(got >> HB);
             mQ = (float)gray_decode(got & (L - 1));
@@ -540,14 +538,17 @@ struct RLanes {
 // computes the rows below.  rl holds R' transposed: rl[d N + e] is the
 // coefficient of s_e in row d (lattice units of row d).  `prune`: the wave
 // stops once no lane with live = true has a metric at or below it (a NaN
-// metric counts as above; all lanes must take part).  FIRST: every rank is 1
-// (path 0), the choice code for higher ranks is left out.
+// metric counts as above; all lanes must take part).  A lane with live =
+// false returns +inf (a finite prune) or a metric of no use: its caller
+// discards it.  FIRST: every rank is 1 (path 0), the choice code for higher
+// ranks is left out.
 template <int N, int L, int PREC, bool FIRST = false, int HSN = kHalfStateN, typename YF, typename RF>
 __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_t *pw, float *decf, float prune,
                                          bool live)
 {
-    float metric = 0.f;
-    const uint64_t live_lanes = lane_mask(live);
+    // lanes that take no part in the stop (live = false) start above any
+    // bound, so the ballot of the metric alone decides it
+    float metric = live ? 0.f : INFINITY;
     // FP32: (s_I, s_Q) of the decided depths, as a float2, or above HSN
     // users as a half2 (small odd integers, exact) that mixed
     // FMAs widen exactly where they read it: the same products and sums in
@@ -631,7 +632,7 @@ __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_
         }
         metric = fmaf(gw, e, metric);
         decf[d >> 2] = fmaf(fmaf(mQ, (float)L, mI), code_weight(d), decf[d >> 2]);
-        if (d + 1 < N && (lane_mask(metric <= prune) & live_lanes) == 0)
+        if (d + 1 < N && lane_mask(metric <= prune) == 0)
             break;
         const float sI = level_of<L>(mI), sQ = level_of<L>(mQ);
         if constexpr (HS) {
