@@ -394,6 +394,22 @@ __device__ __forceinline__ float kth_small(float zI, float zQ, int k, float &mI,
     }
 }
 
+// Lanes of a bitonic compare-exchange step (block size `size`, distance j,
+// rows of npt lanes) that keep the smaller key when lower == up: a constant
+// of the lane pattern, turned into a lane predicate by an inverse ballot (a
+// scalar constant, not a mask computed and held per wave).
+constexpr uint64_t bitonic_keep_low(int size, int j, int npt)
+{
+    uint64_t m = 0;
+    for (int l = 0; l < 64; ++l) {
+        const bool up = size == npt || (l & size) == 0;
+        const bool lower = (l & j) == 0;
+        if (lower == up)
+            m |= 1ull << l;
+    }
+    return m;
+}
+
 // Exact k-th closest point for k > 4, computed by the whole wavefront.  The
 // lanes that need it at this depth are served in rounds: a round takes the
 // received value z of one of them, lane c evaluates constellation point
@@ -426,9 +442,8 @@ __device__ __forceinline__ void kth_wave(bool need, float zI, float zQ, int k, f
 #pragma unroll
             for (int j = size >> 1; j > 0; j >>= 1) {
                 const uint64_t ok = lane_xor_n(key, j);
-                const bool up = size == NPT || (lane & size) == 0;
-                const bool lower = (lane & j) == 0;
-                const bool take = (lower == up) == (ok < key);
+                const bool keep_low = __builtin_amdgcn_inverse_ballot_w64(bitonic_keep_low(size, j, NPT));
+                const bool take = keep_low == (ok < key);
                 key = take ? ok : key;
             }
         }
@@ -516,7 +531,8 @@ struct RUniform {
     cptr<float> dg, rl;
     cptr<uint32_t> rq;
     __device__ __forceinline__ float gw(int d) const { return dg[4 * d]; }
-    __device__ __forceinline__ float gzero(int d) const { return dg[4 * d + 1]; }
+    // R_ll == 0 flag (0.f or 1.f) tested on its bits: a scalar compare
+    __device__ __forceinline__ bool gzero(int d) const { return __float_as_uint(dg[4 * d + 1]) != 0u; }
     __device__ __forceinline__ float2 r(int i) const { return ld2(rl, i); }
     __device__ __forceinline__ uint2 q(int i) const { return make_uint2(rq[2 * i], rq[2 * i + 1]); }
 };
@@ -525,7 +541,7 @@ struct RLanes {
     const float *dg, *rl;
     const uint32_t *rq;
     __device__ __forceinline__ float gw(int d) const { return dg[4 * d]; }
-    __device__ __forceinline__ float gzero(int d) const { return dg[4 * d + 1]; }
+    __device__ __forceinline__ bool gzero(int d) const { return dg[4 * d + 1] != 0.f; }
     __device__ __forceinline__ float2 r(int i) const { return ((const float2 *)rl)[i]; }
     __device__ __forceinline__ uint2 q(int i) const { return ((const uint2 *)rq)[i]; }
 };
@@ -560,7 +576,8 @@ __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_
 #pragma unroll
     for (int d = 0; d < N; ++d) {
         const int k = (pw[d >> 2] >> ((d & 3) * 8)) & 0xff;
-        const float gw = R.gw(d), gzero = R.gzero(d);
+        const float gw = R.gw(d);
+        const bool gzero = R.gzero(d);
         const float2 yd = y(d);
         float zI = yd.x, zQ = yd.y;
         if constexpr (PREC == PREC_FP32) {
@@ -601,7 +618,7 @@ __device__ __forceinline__ float descend(const YF &y, const RF &R, const uint32_
             }
         }
         float mI, mQ, e;  // the chosen point and its squared distance
-        if (gzero != 0.f) {
+        if (gzero) {
             // R_ll = 0: every point is equally far; the k-th in index order
             const int idx = min(max(k - 1, 0), L * L - 1);
             mI = (float)gray_decode(idx >> Axis<L>::HB);
