@@ -318,13 +318,13 @@ constexpr uint32_t zigzag_word(int L, int t)
     return w;
 }
 
-// Ranks 1..3 of one axis (L = 4 or 8): mirrored level values v[t] and
-// squared distances e[t], with the mirror sign s (s = +1: z at or above the
-// level of m0, the level of rank t is s v[t]).  The distance is taken in
+// Ranks 1..R (R <= 3) of one axis (L = 4 or 8): mirrored level values v[t]
+// and squared distances e[t], with the mirror sign s (s = +1: z at or above
+// the level of m0, the level of rank t is s v[t]).  The distance is taken in
 // mirrored coordinates, (s z - v)^2: negation is exact and rounding
 // symmetric, so it is the same bits as (z - s v)^2.
-template <int L>
-__device__ __forceinline__ void axis_ranks3(float z, float m0, float lv0, float (&v)[3], float (&e)[3], float &s)
+template <int L, int R>
+__device__ __forceinline__ void axis_ranks(float z, float m0, float lv0, float (&v)[3], float (&e)[3], float &s)
 {
     static_assert(L == 4 || L == 8, "tabulated zig-zag: 4 or 8 levels an axis");
     constexpr int FW = 32 / L;
@@ -333,10 +333,53 @@ __device__ __forceinline__ void axis_ranks3(float z, float m0, float lv0, float 
     const float zs = s * z;
     const uint32_t off = (uint32_t)fmaf(s, fmaf(m0, (float)FW, -H), H);  // FW m'
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
+    for (int t = 0; t < R; ++t) {
         v[t] = (float)(int)__builtin_amdgcn_sbfe((int)zigzag_word(L, t + 1), off, FW);
         e[t] = square_rn(zs - v[t]);
     }
+}
+
+// Rank 3 or 4 (L = 4 or 8) from the frontier of the per-axis orders; FOUR =
+// false: every lane asks for rank 3.
+template <int L, bool FOUR>
+__device__ __forceinline__ float kth_frontier(float zI, float zQ, int k, float &mI, float lI, float eI,
+                                              float &mQ, float lQ, float eQ)
+{
+    constexpr int R = FOUR ? 3 : 2;
+    float vi[3], ei[3], vq[3], eq[3], sI, sQ;
+    axis_ranks<L, R>(zI, mI, lI, vi, ei, sI);
+    axis_ranks<L, R>(zQ, mQ, lQ, vq, eq, sQ);
+    const float A1 = ei[0] + eQ, A2 = ei[1] + eQ;  // (t, 0)
+    const float B1 = eI + eq[0], B2 = eI + eq[1];  // (0, t)
+    const bool firstI = A1 <= B1;                  // rank 2 = (1,0), else (0,1)
+    const bool t20 = firstI & (A2 <= B1);          // ranks 2, 3 = (1,0), (2,0)
+    const bool t02 = !firstI & (B2 < A1);          // ranks 2, 3 = (0,1), (0,2)
+    bool i1 = !firstI & !t02, i2 = t20, i3 = false;
+    bool q1 = firstI & !t20, q2 = t02, q3 = false, c11 = false;
+    float A3 = 0.f, B3 = 0.f, C = 0.f;
+    if constexpr (FOUR) {
+        A3 = ei[2] + eQ;
+        B3 = eI + eq[2];
+        C = ei[0] + eq[0];  // (1, 1)
+        // rank 4 after (1,0), (2,0): (3,0) or (0,1); after (0,1), (0,2):
+        // (1,0) or (0,3); after (1,0), (0,1): (2,0), (1,1) or (0,2)
+        const bool k3 = k == 3;
+        const bool mid = !t20 & !t02;
+        const bool x20 = (A2 <= C) & (A2 <= B2), x11 = !x20 & (C <= B2);
+        i1 = k3 ? i1 : (t02 & (A1 <= B3));
+        i2 = k3 ? i2 : (mid & x20);
+        i3 = !k3 & t20 & (A3 <= B1);
+        q1 = k3 ? q1 : (t20 & !(A3 <= B1));
+        q2 = k3 ? q2 : (mid & !x20 & !x11);
+        q3 = !k3 & t02 & !(A1 <= B3);
+        c11 = !k3 & mid & x11;
+    }
+    // level index from the mirrored level value: m = (s v + L - 1) / 2
+    const float vI = i3 ? vi[2] : i2 ? vi[1] : vi[0];
+    const float vQ = q3 ? vq[2] : q2 ? vq[1] : vq[0];
+    mI = (i1 | i2 | i3 | c11) ? fmaf(vI, 0.5f * sI, 0.5f * (float)(L - 1)) : mI;
+    mQ = (q1 | q2 | q3 | c11) ? fmaf(vQ, 0.5f * sQ, 0.5f * (float)(L - 1)) : mQ;
+    return i1 ? A1 : i2 ? A2 : i3 ? A3 : q1 ? B1 : q2 ? B2 : q3 ? B3 : C;
 }
 
 // Exact 3rd or 4th closest point from the per-axis orders: ranks 2..4 of
@@ -364,33 +407,11 @@ __device__ __forceinline__ float kth_small(float zI, float zQ, int k, float &mI,
         mQ = inI ? mQ : m1Q;
         return inI ? A1 : inQ ? B1 : e1I + e1Q;
     } else {
-        float vi[3], ei[3], vq[3], eq[3], sI, sQ;
-        axis_ranks3<L>(zI, mI, lI, vi, ei, sI);
-        axis_ranks3<L>(zQ, mQ, lQ, vq, eq, sQ);
-        const float A1 = ei[0] + eQ, A2 = ei[1] + eQ, A3 = ei[2] + eQ;  // (t, 0)
-        const float B1 = eI + eq[0], B2 = eI + eq[1], B3 = eI + eq[2];  // (0, t)
-        const float C = ei[0] + eq[0];                                  // (1, 1)
-        const bool firstI = A1 <= B1;          // rank 2 = (1,0), else (0,1)
-        const bool t20 = firstI & (A2 <= B1);  // ranks 2, 3 = (1,0), (2,0)
-        const bool t02 = !firstI & (B2 < A1);  // ranks 2, 3 = (0,1), (0,2)
-        const bool k3 = k == 3;
-        // rank 4 after (1,0), (2,0): (3,0) or (0,1); after (0,1), (0,2):
-        // (1,0) or (0,3); after (1,0), (0,1): (2,0), (1,1) or (0,2)
-        const bool mid = !t20 & !t02;
-        const bool x20 = (A2 <= C) & (A2 <= B2), x11 = !x20 & (C <= B2);
-        const bool i1 = k3 ? (!firstI & !t02) : (t02 & (A1 <= B3));
-        const bool i2 = k3 ? t20 : (mid & x20);
-        const bool i3 = !k3 & t20 & (A3 <= B1);
-        const bool q1 = k3 ? (firstI & !t20) : (t20 & !(A3 <= B1));
-        const bool q2 = k3 ? t02 : (mid & !x20 & !x11);
-        const bool q3 = !k3 & t02 & !(A1 <= B3);
-        const bool c11 = !k3 & mid & x11;
-        // level index from the mirrored level value: m = (s v + L - 1) / 2
-        const float vI = i3 ? vi[2] : i2 ? vi[1] : vi[0];
-        const float vQ = q3 ? vq[2] : q2 ? vq[1] : vq[0];
-        mI = (i1 | i2 | i3 | c11) ? fmaf(vI, 0.5f * sI, 0.5f * (float)(L - 1)) : mI;
-        mQ = (q1 | q2 | q3 | c11) ? fmaf(vQ, 0.5f * sQ, 0.5f * (float)(L - 1)) : mQ;
-        return i1 ? A1 : i2 ? A2 : i3 ? A3 : q1 ? B1 : q2 ? B2 : q3 ? B3 : C;
+        // the third level of an axis and the compares of rank 4 only where
+        // some lane of the wave asks for rank 4 (a wave-uniform branch)
+        if (__builtin_amdgcn_ballot_w64(k == 4) != 0)
+            return kth_frontier<L, true>(zI, zQ, k, mI, lI, eI, mQ, lQ, eQ);
+        return kth_frontier<L, false>(zI, zQ, k, mI, lI, eI, mQ, lQ, eQ);
     }
 }
 
