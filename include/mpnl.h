@@ -3,10 +3,11 @@
  * non-linear (MPNL) uplink MIMO detection, arXiv 2409.14355 Sec. II
  * ("Background", the MPNL paragraph).
  *
- * The paper states the method only in prose: before transmission the channel
- * alone fixes the relative positions of the N_p most promising solutions;
- * during transmission those N_p candidates are formed and processed in
- * parallel and the best one is the detection result.  This library reads
+ * The paper states the method only in prose: before transmission, the
+ * channel alone decides which N_p rank patterns (per-depth choices of the
+ * k-th closest point) are worth searching; during transmission one candidate
+ * is built from each pattern, all in parallel, and the one with the smallest
+ * metric is the detection result.  This library reads
  * that as (readings listed in the design notes):
  *   a1  sorted QR of every subcarrier's channel, H[:, perm] = Q R
  *       (smallest residual column first, equal norms -> lower column index,
@@ -200,9 +201,9 @@ int mpnl_detect_static(mpnl_ctx *ctx, const void *H, const void *y, int S,
 
 /* ---- slot-resident state (serving) ---------------------------------------- */
 
-/* The part of MPNL that needs only the channel (Sec. II: the positions of
-   the most promising candidates are fixed from the channel before any data
-   arrives): a1 (sorted QR) and a2 (position-vector set) for one slot's
+/* The part of MPNL that needs only the channel (Sec. II: the rank patterns
+   to search depend on the channel alone, so they are settled before any
+   data arrives): a1 (sorted QR) and a2 (position-vector set) for one slot's
    channel; Q, R, perm and the position vectors stay on the device until
    mpnl_slot_release().  The channel is only read by the enqueued work.
    On success *slot receives a handle owned by the context.
